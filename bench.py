@@ -1,0 +1,177 @@
+"""Benchmark of the coupled LB-FD-PF step on one MI355X.
+
+Default workload: the D3Q19 packed sphere bed of 256x128x128 cells, FP32
+populations and fields, one-step F + O -> 2P chemistry (4 species).  A step
+is one launch of the fused kernel: LB collide+stream with interface drag, FD
+transport of T and Y_k with interface heat exchange, Arrhenius reaction
+sub-steps, and FP64 conservation partials.  Inputs are resident in HBM before
+the timed region; the timed region is K steps bracketed by stream
+synchronisation, timed with HIP events on the stream the kernel runs on.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("coupled MLUPS + % HBM roofline; surrogate vs exact-chemistry speedup "
+          "@≤1% T err")
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2310_17214_amd/csrc/lbfd_kernels.inc",
+                  "paper_2310_17214_amd/csrc/lbfd_device.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(name):
+    from paper_2310_17214_amd import workloads as W
+
+    if name == "cfg2":
+        return W.cfg2_bed(precision="fp32")
+    if name == "cfg2_fp64":
+        return W.cfg2_bed(precision="fp64")
+    if name == "cfg1":
+        return W.cfg1_cylinder()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_from_profiles(workload_name, bytes_alg):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, steps=1):
+    """The FP64 CPU oracle, as it stands, on a bounded sample of the same
+    workload: `steps` step(s) of the full grid from the initial state."""
+    from oracle import oracle as O
+
+    wl64 = dict(wl.setup)
+    wl64["precision"] = "fp64"
+    orc = O.Oracle(wl64, wl.phi)
+    orc.init_state(wl.T0, wl.Y0 if wl.setup["ns"] else None)
+    t0 = time.perf_counter()
+    orc.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": wl.cells * steps / dt / 1e6, "unit": "MLUPS", "cores": O.nthreads(),
+            "kind": "oracle",
+            "sample": f"{steps} step(s) of the full {wl.setup['nx']}x{wl.setup['ny']}x"
+                      f"{wl.setup['nz']} grid from the initial state, {dt:.1f} s"}
+
+
+def copy_probe():
+    """A plain device copy of 1 GiB, run under the HBM counters to calibrate
+    FETCH_SIZE / WRITE_SIZE."""
+    import torch
+
+    a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": a.numel() * 4, "copy_probe_bytes_written":
+                      b.numel() * 4}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
+              "(multi-GPU slab decomposition is design-only)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import torch
+
+    from paper_2310_17214_amd import lbfd
+
+    wl = make_workload(args.workload)
+    print(f"bench: {wl.name}, {wl.cells} cells, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    ctx = lbfd.Context(wl.setup, wl.phi, stream=stream)
+    ctx.init_state(wl.T0, wl.Y0 if wl.setup["ns"] else None)
+    ctx.step(args.warmup)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    ctx.step(args.steps)
+    e1.record(stream)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    diag = ctx.diagnostics()
+    mlups = wl.cells * args.steps / (ms * 1e-3) / 1e6
+    bpc = ctx.bytes_per_cell()
+    bytes_launch = bpc * wl.cells
+    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    traffic = traffic_from_profiles(args.workload, bytes_launch)
+    prec = wl.setup.get("precision", "fp64")
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "cells": wl.cells,
+                   "lattice": "D2Q9" if wl.setup["dim"] == 2 else "D3Q19",
+                   "species": wl.setup["ns"], "reactions": len(wl.setup["mech"]["A"]),
+                   "precision": prec, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_cell": bpc,
+                     "kernel": "step_kernel (fused LB+FD+chemistry+partials)"},
+        "diagnostics": {"mass": diag["mass"], "Tmax": diag["Tmax"], "umax": diag["umax"],
+                        "n_flagged_fp64": diag["n_flagged_fp64"],
+                        "n_nonfinite": diag["n_nonfinite"]},
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

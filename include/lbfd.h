@@ -1,0 +1,206 @@
+/*
+ * lbfd.h -- C ABI of the MI355X (gfx950) implementation of the coupled
+ * low-Mach lattice-Boltzmann / finite-difference / phase-field (LB-FD-PF)
+ * time step for reactive gas flow through a particle bed given as a diffuse
+ * solid phase field (Namdar, Norouzi, Varnik, "A low-Mach phase field-lattice
+ * Boltzmann-finite difference model for reactive gas flows propagating
+ * through complex shaped particle assemblies").
+ *
+ * One call of lbfd_step advances every cell by one time step:
+ *   1. LB collision and streaming of the pressure-based populations g_i
+ *      (Sec. 3.3, Eqs. pop-g, body-force, eq-pop-f, eq-pop-g) with the
+ *      interface drag F_drag = -A_u mu phi_f phi_s^2 u / eta^2
+ *      (Sec. 3.2.1, Eq. Fdrag-empirical-law);
+ *   2. FD advection-diffusion of T and Y_k (Sec. 3.2.2, Eq.
+ *      volume-averaged-species-equation-5; Sec. 3.3, Eq.
+ *      energy-transport-DI-version) with the interface heat exchange
+ *      S_I = A_T lambda phi_f phi_s^2 (T_s - T)/eta^2 (Eq. diffusion-heat-flux-3);
+ *   3. per-cell reaction sources omega_k, omega_T (Eqs. 8 and 9) from a plain
+ *      Arrhenius mass-action table, integrated with n_sub explicit sub-steps;
+ *   4. FP64 conservation diagnostics.
+ * Closures: ideal-gas EOS at fixed thermodynamic pressure (Sec. 3.1),
+ * Sutherland viscosity (Sec. 4, Eq. muT), lambda = mu cp/Pr (Eq. lambdaT),
+ * Wilke mixture rules (Sec. 4.4, Eqs. muT_mix, phi_mix, conduct_mix).
+ *
+ * Units: lattice units (dx = dt = 1) except temperatures in kelvin.
+ * Field layout everywhere: x fastest, then y, then z; multi-component fields
+ * component-major.  Host I/O is FP64 whatever the device precision.
+ * Lattices: D2Q9 (dim 2, nz = 1) or D3Q19 (dim 3).  Population order:
+ * rest; +x,-x,+y,-y,+z,-z; then the diagonal pairs (c, -c):
+ *   D2Q9:  (1,1),(-1,-1),(1,-1),(-1,1)
+ *   D3Q19: (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),
+ *          (-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1)
+ *
+ * Ownership: host arrays are read during the call and never retained.  The
+ * device workspace and the HIP stream belong to the caller, must outlive the
+ * context, and the library never allocates or frees device memory.
+ * Errors: every call returns lbfd_status (0 = OK, negative = error) and no
+ * C++ exception crosses the ABI; lbfd_last_error gives the message.  set_*
+ * calls leave the context unchanged on error.  A context is bound to one
+ * stream and is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LBFD_H
+#define LBFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBFD_MAX_SPECIES 16
+#define LBFD_MAX_REACTIONS 32
+
+typedef struct lbfd_ctx lbfd_ctx;
+
+typedef enum {
+    LBFD_OK = 0,
+    LBFD_E_INVAL = -1,       /* bad argument or parameter out of the stable range */
+    LBFD_E_NOMEM = -2,       /* workspace too small                              */
+    LBFD_E_DEVICE = -3,      /* HIP runtime error                                */
+    LBFD_E_STATE = -4,       /* call out of order (e.g. step before init_state)  */
+    LBFD_E_NUMERIC = -5,     /* non-finite values appeared in a step             */
+    LBFD_E_UNSUPPORTED = -6  /* valid request this build does not implement      */
+} lbfd_status;
+
+typedef enum { LBFD_FP64 = 0, LBFD_FP32 = 1 } lbfd_precision;
+
+/* LB boundary kind per face (-x,+x,-y,+y,-z,+z).  The velocity inlet is
+ * allowed on the -x face only and the pressure outlet on the +x face only. */
+typedef enum {
+    LBFD_LB_PERIODIC = 0,
+    LBFD_LB_WALL = 1,             /* halfway bounce-back (no slip)                 */
+    LBFD_LB_VELOCITY_INLET = 2,   /* equilibrium at (rho_in, u_in, local P_h)      */
+    LBFD_LB_PRESSURE_OUTLET = 3   /* equilibrium at (local rho, local u, P_h = 0)  */
+} lbfd_lb_bc;
+
+/* FD boundary kind per face; the +/- faces of an axis must both be periodic
+ * or both non-periodic, and so must the LB kinds. */
+typedef enum {
+    LBFD_FD_PERIODIC = 0,
+    LBFD_FD_DIRICHLET = 1,       /* cell-centred ghost at the face value           */
+    LBFD_FD_ZERO_GRADIENT = 2    /* ghost copies the boundary cell                 */
+} lbfd_fd_bc;
+
+typedef struct {
+    int32_t dim, nx, ny, nz;     /* dim 2 -> D2Q9 (nz must be 1), dim 3 -> D3Q19   */
+    int32_t precision;           /* lbfd_precision                                 */
+    int32_t n_species;           /* 0 .. LBFD_MAX_SPECIES                          */
+    int32_t lb_bc[6];            /* lbfd_lb_bc per face                            */
+    int32_t fd_bc[6];            /* lbfd_fd_bc per face                            */
+} lbfd_grid;
+
+typedef struct {
+    double A_u, A_T, eta, T_solid;   /* interface coupling (Eqs. Fdrag-empirical-law,
+                                        diffusion-heat-flux-3), interface thickness
+                                        in cells, solid temperature [K]             */
+    double Pr, cp, rho_in, T_in, nu_in, sutherland_S;
+    int32_t mu_model;                /* 0 constant viscosity, 1 Sutherland          */
+    int32_t transport_model;         /* 0 single gas (lambda = mu cp/Pr),
+                                        1 Wilke mixture rules with mu*_k            */
+    double u_in[3], body_force[3];   /* inlet velocity, body force                  */
+    double Y_in[LBFD_MAX_SPECIES];   /* inlet composition; fixes the reference molar
+                                        mass of the EOS                             */
+    double Le[LBFD_MAX_SPECIES];     /* Lewis numbers: rho D_k = lambda/(cp Le_k)   */
+    double fd_face[6][1 + LBFD_MAX_SPECIES]; /* Dirichlet values per face: T, Y_k   */
+    int32_t n_sub;                   /* explicit reaction sub-steps per step (>= 1) */
+    double ign_threshold;            /* FP32 mode: a cell's reaction step runs in
+                                        FP64 when |omega_T| dt/(rho cp) exceeds it [K] */
+} lbfd_params;
+
+typedef struct {
+    int32_t n_species, n_reactions;
+    const double* M;          /* [ns] molar masses                                */
+    const double* dhf;        /* [ns] formation enthalpy per unit mass [cp*K]     */
+    const double* mu_star;    /* [ns] species viscosity / reference viscosity     */
+    const int32_t* nu_f;      /* [nr][ns] reactant stoichiometric coefficients    */
+    const int32_t* nu_r;      /* [nr][ns] product stoichiometric coefficients     */
+    const double* A;          /* [nr] k_f = A T^beta exp(-theta/T)                */
+    const double* beta;       /* [nr]                                             */
+    const double* theta;      /* [nr] activation temperature [K]                  */
+    const int32_t* reversible;/* [nr] 0/1; k_r = k_f / exp(lnKc_a + lnKc_b/T)     */
+    const double* lnKc_a;     /* [nr]                                             */
+    const double* lnKc_b;     /* [nr]                                             */
+} lbfd_mechanism;
+
+typedef struct {
+    double mass;                          /* sum rho                                 */
+    double species_mass[LBFD_MAX_SPECIES];/* sum rho Y_k                             */
+    double enthalpy;                      /* sum rho (cp T + sum_k dhf_k Y_k)        */
+    double kinetic;                       /* sum rho |u|^2/2 of the last LB step     */
+    double umax, Tmin, Tmax;
+    int64_t n_nonfinite, n_tau_bad, n_negY, n_flagged_fp64, n_fallback, step;
+} lbfd_diag;
+
+typedef enum {
+    LBFD_F_RHO = 0,          /* EOS of the current state                          */
+    LBFD_F_U = 1,            /* component 0..dim-1; moments of the current populations */
+    LBFD_F_T = 2,
+    LBFD_F_Y = 3,            /* component 0..ns-1                                 */
+    LBFD_F_PH = 4,           /* hydrodynamic pressure of the current populations  */
+    LBFD_F_POPULATIONS = 5,  /* component 0..Q-1, post-stream, natural layout     */
+    LBFD_F_DIVU = 6          /* thermal velocity divergence used by the next step */
+} lbfd_field;
+
+/* phase bits of lbfd_step_phase (test hook; lbfd_step runs all three) */
+enum { LBFD_PHASE_LB = 1, LBFD_PHASE_FD = 2, LBFD_PHASE_CHEM = 4, LBFD_PHASE_ALL = 7 };
+
+/* Bytes of device workspace a grid needs (256-byte aligned base expected). */
+lbfd_status lbfd_workspace_bytes(const lbfd_grid* grid, size_t* bytes);
+
+/* Create a context on the current HIP device.  dev_workspace: caller-owned
+ * device buffer of at least lbfd_workspace_bytes; hip_stream: hipStream_t (or
+ * NULL for the null stream) on which every kernel of this context runs. */
+lbfd_status lbfd_create(const lbfd_grid* grid, void* dev_workspace, size_t bytes,
+                        void* hip_stream, lbfd_ctx** out);
+
+/* Static solid phase field phi_s in [0, 1] (host, nx*ny*nz doubles). */
+lbfd_status lbfd_set_phase_field(lbfd_ctx* ctx, const double* phi_solid);
+
+/* Reaction mechanism; n_species must equal the grid's. */
+lbfd_status lbfd_set_mechanism(lbfd_ctx* ctx, const lbfd_mechanism* mech);
+
+/* Physical and coupling parameters; rejects unstable values (tau at the inlet
+ * state <= 0.5 + 1e-3, |u_in| > 0.1, eta <= 0, n_sub < 1, ...). */
+lbfd_status lbfd_set_params(lbfd_ctx* ctx, const lbfd_params* params);
+
+/* Initial state (host FP64): T[N], Y[ns*N] (NULL iff ns == 0), u[dim*N] or
+ * NULL (rest).  Sets rho from the EOS, divu = 0, P_h = 0 and the populations
+ * to equilibrium; clears the diagnostics.  Needs phase field, params and (ns >
+ * 0) mechanism first. */
+lbfd_status lbfd_init_state(lbfd_ctx* ctx, const double* T, const double* Y, const double* u);
+
+/* Overwrite the post-stream populations (Q*N doubles, natural layout) and the
+ * thermal divergence (N doubles, may be NULL); together with lbfd_init_state
+ * this restores a checkpoint written with lbfd_read. */
+lbfd_status lbfd_set_populations(lbfd_ctx* ctx, const double* g, const double* divu);
+
+/* Enqueue n coupled steps on the context's stream; returns without waiting. */
+lbfd_status lbfd_step(lbfd_ctx* ctx, int32_t n);
+
+/* Enqueue n steps running only the phases in phase_mask (test hook).  Without
+ * LB the velocity is zero and populations are untouched; without FD, T and Y
+ * enter the reaction step unchanged; without CHEM no reaction is applied. */
+lbfd_status lbfd_step_phase(lbfd_ctx* ctx, int32_t n, int32_t phase_mask);
+
+/* Copy one field component to host (waits for the stream). */
+lbfd_status lbfd_read(lbfd_ctx* ctx, int32_t field, int32_t component, double* host_out);
+
+/* Conservation sums of the state after the last step and cumulative counters
+ * (waits for the stream); returns LBFD_E_NUMERIC if n_nonfinite > 0. */
+lbfd_status lbfd_diagnostics(lbfd_ctx* ctx, lbfd_diag* out);
+
+/* Wait for the context's stream. */
+lbfd_status lbfd_synchronize(lbfd_ctx* ctx);
+
+/* Algorithmic HBM bytes one cell moves in one lbfd_step on this grid. */
+lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* ctx, double* bytes);
+
+lbfd_status lbfd_destroy(lbfd_ctx* ctx);
+const char* lbfd_last_error(const lbfd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -633,8 +633,9 @@ int orc_init_state(orc_ctx* o, const double* T, const double* Y, const double* u
     return 0;
 }
 
-int orc_set_populations(orc_ctx* o, const double* g) {
+int orc_set_populations(orc_ctx* o, const double* g, const double* divu) {
     memcpy(o->g, g, (size_t)o->Q * o->N * sizeof(double));
+    if (divu) memcpy(o->divu, divu, o->N * sizeof(double));
     return 0;
 }
 

@@ -65,8 +65,9 @@ orc_ctx* orc_create(const orc_setup* s, const double* phi_solid);
 void     orc_destroy(orc_ctx* o);
 /* T[N], Y[ns*N] (may be NULL when ns == 0), u[dim*N] (NULL -> at rest) */
 int      orc_init_state(orc_ctx* o, const double* T, const double* Y, const double* u);
-/* overwrite the post-stream populations (Q*N, natural layout) */
-int      orc_set_populations(orc_ctx* o, const double* g);
+/* overwrite the post-stream populations (Q*N, natural layout) and, if not
+ * NULL, the thermal divergence (N) -- restores a saved state */
+int      orc_set_populations(orc_ctx* o, const double* g, const double* divu);
 int      orc_step(orc_ctx* o, int32_t n, int32_t phase_mask);
 int      orc_read(const orc_ctx* o, int32_t field, int32_t comp, double* out);
 void     orc_diag(const orc_ctx* o, double* out /* ORC_D_LEN */);

@@ -68,7 +68,7 @@ def lib():
         L.orc_create.argtypes = [C.POINTER(Setup), dp]
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_init_state.argtypes = [C.c_void_p, dp, dp, dp]
-        L.orc_set_populations.argtypes = [C.c_void_p, dp]
+        L.orc_set_populations.argtypes = [C.c_void_p, dp, dp]
         L.orc_step.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.orc_read.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp]
         L.orc_diag.argtypes = [C.c_void_p, dp]
@@ -150,10 +150,11 @@ class Oracle:
         ub = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
         lib().orc_init_state(self._h, _dp(T), _dp(Yb), None if ub is None else _dp(ub))
 
-    def set_populations(self, g):
+    def set_populations(self, g, divu=None):
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
         assert g.size == self.Q * self.N
-        lib().orc_set_populations(self._h, _dp(g))
+        d = None if divu is None else np.ascontiguousarray(divu, dtype=np.float64).reshape(-1)
+        lib().orc_set_populations(self._h, _dp(g), None if d is None else _dp(d))
 
     def step(self, n=1, mask=PH_ALL):
         lib().orc_step(self._h, int(n), int(mask))

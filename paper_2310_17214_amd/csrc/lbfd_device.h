@@ -1,0 +1,271 @@
+// lbfd_device.h -- device-side data and per-cell arithmetic of the fused
+// coupled step for gfx950.  Included by the kernel translation units (one per
+// precision) and, for the parameter block layout only, by the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbfd {
+
+// array extent for a compile-time species bound (zero-length arrays are not allowed)
+#define LBFD_NA(n) ((n) > 0 ? (n) : 1)
+
+constexpr int MAXS = 16;
+constexpr int MAXR = 32;
+constexpr int BLOCK = 256;       // threads per workgroup: 4 wave64
+constexpr int DIAG_STRIDE = 32;  // doubles of partials per workgroup
+enum {
+    DG_MASS = 0, DG_SP = 1, DG_ENTH = 17, DG_KIN = 18, DG_UMAX = 19, DG_TMIN = 20,
+    DG_TMAX = 21, DG_NONFIN = 22, DG_TAUBAD = 23, DG_NEGY = 24, DG_FLAG = 25, DG_FALLBACK = 26,
+    DG_COUNT = 27
+};
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INLET = 2, BC_OUTLET = 3 };
+enum { FD_PERIODIC = 0, FD_DIRICHLET = 1, FD_NEUMANN = 2 };
+enum { PH_LB = 1, PH_FD = 2, PH_CHEM = 4 };
+
+// Every constant the kernels read, in the kernel's arithmetic type.  Lives in
+// the device workspace and is read with wave-uniform (scalar) loads.
+template <typename R>
+struct Par {
+    int nx, ny, nz, ns, nr;
+    int n_sub, mu_model, transport, corr, any_beta;
+    int lb_bc[6], fd_bc[6];
+    R A_u, A_T, inv_eta2, T_s, cp, inv_cp, inv_Pr, rho_in, T_in, mu_ref, S_T_in, S;
+    R rho_ref;        // rho_in * T_in / Mbar_in  (EOS numerator)
+    R theta_ign, h_sub;
+    R u_in[3], F_b[3];
+    R fd_face[6][1 + MAXS];
+    R rD_fac[MAXS];   // 1/(cp Le_k)
+    R M[MAXS], invM[MAXS], dhf[MAXS], mu_star[MAXS];
+    R Phi[MAXS][MAXS];
+    R A[MAXR], beta[MAXR], theta[MAXR], lnKc_a[MAXR], lnKc_b[MAXR];
+    int rev[MAXR];
+    int8_t nu_f[MAXR][MAXS], nu_r[MAXR][MAXS], nu_d[MAXR][MAXS];
+};
+
+// ------------------------------------------------------------------ lattice
+template <int D> struct Lat;
+template <> struct Lat<2> {
+    static constexpr int Q = 9;
+    static constexpr int cx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+    static constexpr int cy[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                    1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+template <> struct Lat<3> {
+    static constexpr int Q = 19;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr double w[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                     1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// ------------------------------------------------------------- arithmetic
+// FP32 mode uses the hardware reciprocal / square root / exp2 / log2
+// (about 1 ulp); the FP64 mode uses correctly rounded division and the
+// device library's exp and log.
+template <typename R> __device__ __forceinline__ R rcp(R x);
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+template <typename R> __device__ __forceinline__ R dvd(R a, R b);
+template <> __device__ __forceinline__ float dvd<float>(float a, float b) {
+    return a * __builtin_amdgcn_rcpf(b);
+}
+template <> __device__ __forceinline__ double dvd<double>(double a, double b) { return a / b; }
+template <typename R> __device__ __forceinline__ R fsqrt(R x);
+template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
+template <typename R> __device__ __forceinline__ R fexp(R x);
+template <> __device__ __forceinline__ float fexp<float>(float x) { return __expf(x); }
+template <> __device__ __forceinline__ double fexp<double>(double x) { return exp(x); }
+template <typename R> __device__ __forceinline__ R flog(R x);
+template <> __device__ __forceinline__ float flog<float>(float x) { return __logf(x); }
+template <> __device__ __forceinline__ double flog<double>(double x) { return log(x); }
+
+// ----------------------------------------------------------------- closures
+// Ideal-gas density at fixed thermodynamic pressure: rho = rho_in (T_in/T)(M/M_in).
+template <typename R, int NSM>
+__device__ __forceinline__ R eos(const Par<R>& P, R T, const R* Y) {
+    if constexpr (NSM == 0) {
+        return P.rho_in * dvd(P.T_in, T);
+    } else {
+        R im = R(0);
+#pragma unroll
+        for (int k = 0; k < NSM; ++k)
+            if (k < P.ns) im += Y[k] * P.invM[k];
+        return dvd(P.rho_ref, T * im);
+    }
+}
+
+// Sutherland law as a ratio to the inlet viscosity.
+template <typename R>
+__device__ __forceinline__ R sutherland(const Par<R>& P, R T) {
+    if (P.mu_model == 0) return R(1);
+    R x = dvd(T, P.T_in);
+    return dvd(x * fsqrt(x) * P.S_T_in, T + P.S);
+}
+
+// Viscosity and conductivity of one state (single gas or Wilke mixture).
+template <typename R, int NSM>
+__device__ __forceinline__ void transport(const Par<R>& P, R T, const R* Y, R& mu, R& lam) {
+    R mu0 = P.mu_ref * sutherland(P, T);
+    if constexpr (NSM > 0) {
+        if (P.transport != 0) {
+            R X[LBFD_NA(NSM)], im = R(0);
+#pragma unroll
+            for (int k = 0; k < NSM; ++k)
+                if (k < P.ns) im += Y[k] * P.invM[k];
+            R mbar = rcp(im);
+#pragma unroll
+            for (int k = 0; k < NSM; ++k) X[k] = (k < P.ns) ? Y[k] * mbar * P.invM[k] : R(0);
+            R m = R(0), l1 = R(0), l2 = R(0);
+#pragma unroll
+            for (int k = 0; k < NSM; ++k) {
+                if (k >= P.ns) continue;
+                R den = R(0);
+#pragma unroll
+                for (int j = 0; j < NSM; ++j)
+                    if (j < P.ns) den += P.Phi[k][j] * X[j];
+                R muk = P.mu_star[k] * mu0;
+                R lamk = muk * P.cp * P.inv_Pr;
+                m += dvd(muk * X[k], den);
+                l1 += X[k] * lamk;
+                l2 += dvd(X[k], lamk);
+            }
+            mu = m;
+            lam = R(0.5) * (l1 + rcp(l2));
+            return;
+        }
+    }
+    mu = mu0;
+    lam = mu0 * P.cp * P.inv_Pr;
+}
+
+// e_i = c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2) with cs2 = 1/3
+template <typename R>
+__device__ __forceinline__ R eq_e(R cu, R uu) {
+    return R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+}
+
+// ---------------------------------------------------------------- chemistry
+// Mass-action Arrhenius production rates (omega_k = M_k sum_j s_kj Q_j,
+// omega_T = -sum_k dh_k omega_k), evaluated in type C.
+template <typename C, int NSM>
+__device__ __forceinline__ void rates(const Par<C>& P, C T, const C* Y, C rho, C* wk, C& wT) {
+    C X[LBFD_NA(NSM)];
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) {
+        X[k] = rho * Y[k] * P.invM[k];
+        wk[k] = C(0);
+    }
+    const C invT = rcp(T);
+    const C lnT = P.any_beta ? flog(T) : C(0);
+    for (int j = 0; j < P.nr; ++j) {
+        C kf = P.A[j] * fexp(P.beta[j] * lnT - P.theta[j] * invT);
+        C qf = kf;
+#pragma unroll
+        for (int k = 0; k < NSM; ++k) {
+            int e = P.nu_f[j][k];
+            if (e > 0) qf *= X[k];
+            if (e > 1) qf *= X[k];
+            if (e > 2) qf *= X[k];
+        }
+        C Qj = qf;
+        if (P.rev[j]) {
+            C qr = kf * fexp(-(P.lnKc_a[j] + P.lnKc_b[j] * invT));
+#pragma unroll
+            for (int k = 0; k < NSM; ++k) {
+                int e = P.nu_r[j][k];
+                if (e > 0) qr *= X[k];
+                if (e > 1) qr *= X[k];
+                if (e > 2) qr *= X[k];
+            }
+            Qj -= qr;
+        }
+#pragma unroll
+        for (int k = 0; k < NSM; ++k) {
+            int d = P.nu_d[j][k];
+            if (d != 0) wk[k] += C(d) * Qj;
+        }
+    }
+    C w = C(0);
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) {
+        wk[k] = P.M[k] * wk[k];
+        w -= P.dhf[k] * wk[k];
+    }
+    wT = w;
+}
+
+// One explicit Euler sub-step from rates already evaluated at (T, Y, rho).
+template <typename C, int NSM>
+__device__ __forceinline__ void chem_apply(const Par<C>& P, C& T, C* Y, C rho, const C* wk, C wT) {
+    const C hr = P.h_sub * rcp(rho);
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) Y[k] = Y[k] + hr * wk[k];
+    T = T + hr * wT * P.inv_cp;
+}
+
+// n_sub explicit Euler sub-steps at constant pressure, in type C; the first
+// sub-step may reuse rates evaluated by the caller.
+template <typename C, int NSM>
+__device__ __forceinline__ void chem_integrate(const Par<C>& P, C& T, C* Y, int first = 0) {
+    C wk[LBFD_NA(NSM)], wT;
+    for (int n = first; n < P.n_sub; ++n) {
+        const C rho = eos<C, NSM>(P, T, Y);
+        rates<C, NSM>(P, T, Y, rho, wk, wT);
+        chem_apply<C, NSM>(P, T, Y, rho, wk, wT);
+    }
+}
+
+// ------------------------------------------------------------ kernel args
+template <typename R>
+struct StepArgs {
+    R* g;                 // [Q][N] populations (AA layout)
+    const R* T_cur;       // [N]
+    R* T_nxt;             // [N]
+    const R* Y_cur;       // [ns][N]
+    R* Y_nxt;             // [ns][N]
+    R* divu;              // [N] (read, then overwritten in place)
+    const R* phi;         // [N] solid fraction
+    double* partials;     // [nblocks][DIAG_STRIDE]
+    const Par<R>* P;
+    const Par<double>* PD;
+    int N;
+    int nblocks;          // real workgroups (grid may be padded to a multiple of 8)
+    int nbx, nby;         // 64 x 4 cell tiles along x and y
+    int odd;              // AA parity of this step
+    int phase;            // PH_* mask
+    int diag;             // write diagnostics partials
+};
+
+template <typename R>
+struct MacroArgs {
+    const R* g;
+    const R* T;
+    const R* Y;
+    const R* divu;
+    const R* phi;
+    double* out;          // [5][N]: rho, u_x, u_y, u_z, P_h
+    const Par<R>* P;
+    const Par<double>* PD;
+    int N, nblocks, odd;
+};
+
+template <typename R>
+struct InitArgs {
+    R* g;
+    const R* T;
+    const R* Y;
+    const double* u;      // [dim][N] or null
+    R* divu;
+    const Par<R>* P;
+    int N;
+};
+
+}  // namespace lbfd

@@ -1,0 +1,32 @@
+// lbfd_kernels_f64.hip -- double instantiations of the fused step, read and
+// init kernels (D2Q9/D3Q19 x species bound 0/4/9/16).
+#include "lbfd_device.h"
+#include "lbfd_kernels.inc"
+#include "lbfd_launch.h"
+
+namespace lbfd {
+hipError_t launch_step_f64(int dim, int nsm, const StepArgs<double>& a, int grid, hipStream_t s) {
+    switch (nsm) {
+    case 0: return launch_step_t<double, 0>(dim, a, grid, s);
+    case 4: return launch_step_t<double, 4>(dim, a, grid, s);
+    case 9: return launch_step_t<double, 9>(dim, a, grid, s);
+    default: return launch_step_t<double, 16>(dim, a, grid, s);
+    }
+}
+hipError_t launch_macro_f64(int dim, int nsm, const MacroArgs<double>& a, int grid, hipStream_t s) {
+    switch (nsm) {
+    case 0: return launch_macro_t<double, 0>(dim, a, grid, s);
+    case 4: return launch_macro_t<double, 4>(dim, a, grid, s);
+    case 9: return launch_macro_t<double, 9>(dim, a, grid, s);
+    default: return launch_macro_t<double, 16>(dim, a, grid, s);
+    }
+}
+hipError_t launch_init_f64(int dim, int nsm, const InitArgs<double>& a, int grid, hipStream_t s) {
+    switch (nsm) {
+    case 0: return launch_init_t<double, 0>(dim, a, grid, s);
+    case 4: return launch_init_t<double, 4>(dim, a, grid, s);
+    case 9: return launch_init_t<double, 9>(dim, a, grid, s);
+    default: return launch_init_t<double, 16>(dim, a, grid, s);
+    }
+}
+}  // namespace lbfd

@@ -1,0 +1,704 @@
+// lbfd_runtime.hip -- host runtime behind the C ABI of include/lbfd.h:
+// validation, workspace carving, parameter tables, step sequencing on the
+// caller's stream, field reads and the deterministic diagnostics reduction.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbfd.h"
+#include "lbfd_device.h"
+#include "lbfd_launch.h"
+
+using namespace lbfd;
+
+namespace {
+
+struct HostMech {
+    int ns = 0, nr = 0;
+    std::vector<double> M, dhf, mu_star, A, beta, theta, lnKc_a, lnKc_b;
+    std::vector<int> nu_f, nu_r, rev;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t g, T0, T1, Y0, Y1, divu, phi, part, parf, pard, scratch, red, total;
+    int nbx, nby, nblocks, grid;  // step kernel: 64 x 4 tiles, grid padded to 8 XCDs
+    int nlin;                     // one-cell-per-thread kernels
+};
+
+int lattice_q(int dim) { return dim == 2 ? 9 : 19; }
+
+Layout make_layout(const lbfd_grid& gr) {
+    Layout L;
+    const size_t N = (size_t)gr.nx * gr.ny * gr.nz;
+    const size_t s = gr.precision == LBFD_FP32 ? 4 : 8;
+    const int Q = lattice_q(gr.dim);
+    L.nbx = (gr.nx + 63) / 64;
+    L.nby = (gr.ny + 3) / 4;
+    L.nblocks = L.nbx * L.nby * gr.nz;
+    L.grid = (L.nblocks + 7) / 8 * 8;
+    L.nlin = (int)((N + BLOCK - 1) / BLOCK);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.g = take(Q * N * s);
+    L.T0 = take(N * s);
+    L.T1 = take(N * s);
+    L.Y0 = take((size_t)gr.n_species * N * s);
+    L.Y1 = take((size_t)gr.n_species * N * s);
+    L.divu = take(N * s);
+    L.phi = take(N * s);
+    L.part = take((size_t)L.nblocks * DIAG_STRIDE * sizeof(double));
+    L.parf = take(sizeof(Par<float>));
+    L.pard = take(sizeof(Par<double>));
+    L.scratch = take(5 * N * sizeof(double));
+    L.red = take(64 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int nsm_bucket(int ns) { return ns == 0 ? 0 : ns <= 4 ? 4 : ns <= 9 ? 9 : 16; }
+
+__global__ void reduce_partials(const double* __restrict__ part, int nblocks, int ns,
+                                double* __restrict__ out) {
+    __shared__ double sh[BLOCK];
+    const int t = threadIdx.x;
+    for (int s = 0; s < DG_COUNT; ++s) {
+        if (s >= DG_SP + ns && s < DG_ENTH) {
+            if (t == 0) out[s] = 0.0;
+            continue;
+        }
+        const bool mx = s == DG_UMAX || s == DG_TMAX, mn = s == DG_TMIN;
+        double acc = mx ? -1e300 : mn ? 1e300 : 0.0;
+        for (int b = t; b < nblocks; b += BLOCK) {
+            const double v = part[(size_t)b * DIAG_STRIDE + s];
+            acc = mx ? fmax(acc, v) : mn ? fmin(acc, v) : acc + v;
+        }
+        sh[t] = acc;
+        __syncthreads();
+        for (int w = BLOCK / 2; w > 0; w >>= 1) {
+            if (t < w) {
+                const double v = sh[t + w];
+                sh[t] = mx ? fmax(sh[t], v) : mn ? fmin(sh[t], v) : sh[t] + v;
+            }
+            __syncthreads();
+        }
+        if (t == 0) out[s] = sh[0];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+struct lbfd_ctx {
+    lbfd_grid grid;
+    Layout L;
+    int dim, Q, ns, nsm;
+    size_t N;
+    bool fp32;
+    int device;
+    hipStream_t stream;
+    char* ws;
+    lbfd_params params;
+    HostMech mech;
+    bool have_phi = false, have_params = false, have_mech = false, have_state = false;
+    int cur = 0, odd = 0;
+    int64_t steps = 0;
+    std::string err;
+};
+
+namespace {
+
+lbfd_status fail(lbfd_ctx* c, lbfd_status st, const std::string& msg) {
+    if (c) c->err = msg;
+    return st;
+}
+
+lbfd_status hip_check(lbfd_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return LBFD_OK;
+    return fail(c, LBFD_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+T* dptr(lbfd_ctx* c, size_t off) {
+    return reinterpret_cast<T*>(c->ws + off);
+}
+
+// Wilke interaction coefficient Phi_kj of the mixture viscosity rule.
+double wilke(double muk, double muj, double Mk, double Mj) {
+    const double a = 1.0 + std::sqrt((muk / muj) * std::sqrt(Mj / Mk));
+    return a * a / (std::sqrt(8.0) * std::sqrt(1.0 + Mk / Mj));
+}
+
+template <typename R>
+Par<R> build_par(const lbfd_ctx* c) {
+    Par<R> P;
+    std::memset(&P, 0, sizeof(P));
+    const lbfd_params& p = c->params;
+    const lbfd_grid& g = c->grid;
+    P.nx = g.nx;
+    P.ny = g.ny;
+    P.nz = g.nz;
+    P.ns = c->ns;
+    P.nr = c->ns > 0 ? c->mech.nr : 0;
+    P.n_sub = p.n_sub;
+    P.mu_model = p.mu_model;
+    P.transport = p.transport_model;
+    for (int f = 0; f < 6; ++f) {
+        P.lb_bc[f] = g.lb_bc[f];
+        P.fd_bc[f] = g.fd_bc[f];
+        for (int k = 0; k <= c->ns; ++k) P.fd_face[f][k] = (R)p.fd_face[f][k];
+    }
+    P.A_u = (R)p.A_u;
+    P.A_T = (R)p.A_T;
+    P.inv_eta2 = (R)(1.0 / (p.eta * p.eta));
+    P.T_s = (R)p.T_solid;
+    P.cp = (R)p.cp;
+    P.inv_cp = (R)(1.0 / p.cp);
+    P.inv_Pr = (R)(1.0 / p.Pr);
+    P.rho_in = (R)p.rho_in;
+    P.T_in = (R)p.T_in;
+    P.mu_ref = (R)(p.rho_in * p.nu_in);
+    P.S = (R)p.sutherland_S;
+    P.S_T_in = (R)(p.T_in + p.sutherland_S);
+    P.theta_ign = (R)p.ign_threshold;
+    P.h_sub = (R)(1.0 / p.n_sub);
+    for (int a = 0; a < 3; ++a) {
+        P.u_in[a] = (R)(a < c->dim ? p.u_in[a] : 0.0);
+        P.F_b[a] = (R)(a < c->dim ? p.body_force[a] : 0.0);
+    }
+    double im_in = 0.0;
+    int corr = 0;
+    for (int k = 0; k < c->ns; ++k) {
+        P.rD_fac[k] = (R)(1.0 / (p.cp * p.Le[k]));
+        if (p.Le[k] != p.Le[0]) corr = 1;
+        P.M[k] = (R)c->mech.M[k];
+        P.invM[k] = (R)(1.0 / c->mech.M[k]);
+        P.dhf[k] = (R)c->mech.dhf[k];
+        P.mu_star[k] = (R)c->mech.mu_star[k];
+        im_in += p.Y_in[k] / c->mech.M[k];
+    }
+    P.corr = corr;
+    P.any_beta = 0;
+    for (int j = 0; j < P.nr; ++j)
+        if (c->mech.beta[j] != 0.0) P.any_beta = 1;
+    P.rho_ref = c->ns > 0 ? (R)(p.rho_in * p.T_in / (1.0 / im_in)) : (R)(p.rho_in * p.T_in);
+    for (int k = 0; k < c->ns; ++k)
+        for (int j = 0; j < c->ns; ++j)
+            P.Phi[k][j] =
+                (R)wilke(c->mech.mu_star[k], c->mech.mu_star[j], c->mech.M[k], c->mech.M[j]);
+    for (int j = 0; j < P.nr; ++j) {
+        P.A[j] = (R)c->mech.A[j];
+        P.beta[j] = (R)c->mech.beta[j];
+        P.theta[j] = (R)c->mech.theta[j];
+        P.lnKc_a[j] = (R)c->mech.lnKc_a[j];
+        P.lnKc_b[j] = (R)c->mech.lnKc_b[j];
+        P.rev[j] = c->mech.rev[j];
+        for (int k = 0; k < c->ns; ++k) {
+            const int f = c->mech.nu_f[j * c->ns + k], r = c->mech.nu_r[j * c->ns + k];
+            P.nu_f[j][k] = (int8_t)f;
+            P.nu_r[j][k] = (int8_t)r;
+            P.nu_d[j][k] = (int8_t)(r - f);
+        }
+    }
+    return P;
+}
+
+bool ready_for_tables(const lbfd_ctx* c) { return c->have_params && (c->ns == 0 || c->have_mech); }
+
+lbfd_status upload_tables(lbfd_ctx* c) {
+    if (!ready_for_tables(c)) return LBFD_OK;
+    Par<double> pd = build_par<double>(c);
+    Par<float> pf = build_par<float>(c);
+    lbfd_status st = hip_check(c, hipMemcpyAsync(dptr<char>(c, c->L.pard), &pd, sizeof(pd),
+                                                 hipMemcpyHostToDevice, c->stream),
+                               "upload parameters");
+    if (st) return st;
+    st = hip_check(c, hipMemcpyAsync(dptr<char>(c, c->L.parf), &pf, sizeof(pf),
+                                     hipMemcpyHostToDevice, c->stream),
+                   "upload parameters");
+    if (st) return st;
+    return hip_check(c, hipStreamSynchronize(c->stream), "upload parameters");
+}
+
+// host FP64 -> device field of the context's precision
+lbfd_status upload_field(lbfd_ctx* c, size_t off, const double* src, size_t n) {
+    if (c->fp32) {
+        std::vector<float> tmp(n);
+        for (size_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
+        lbfd_status st = hip_check(
+            c, hipMemcpyAsync(dptr<char>(c, off), tmp.data(), n * 4, hipMemcpyHostToDevice, c->stream),
+            "upload");
+        if (st) return st;
+        return hip_check(c, hipStreamSynchronize(c->stream), "upload");
+    }
+    lbfd_status st = hip_check(
+        c, hipMemcpyAsync(dptr<char>(c, off), src, n * 8, hipMemcpyHostToDevice, c->stream), "upload");
+    if (st) return st;
+    return hip_check(c, hipStreamSynchronize(c->stream), "upload");
+}
+
+lbfd_status download_field(lbfd_ctx* c, size_t off, double* dst, size_t n) {
+    if (c->fp32) {
+        std::vector<float> tmp(n);
+        lbfd_status st = hip_check(
+            c, hipMemcpyAsync(tmp.data(), dptr<char>(c, off), n * 4, hipMemcpyDeviceToHost, c->stream),
+            "download");
+        if (st) return st;
+        st = hip_check(c, hipStreamSynchronize(c->stream), "download");
+        if (st) return st;
+        for (size_t i = 0; i < n; ++i) dst[i] = tmp[i];
+        return LBFD_OK;
+    }
+    lbfd_status st = hip_check(
+        c, hipMemcpyAsync(dst, dptr<char>(c, off), n * 8, hipMemcpyDeviceToHost, c->stream), "download");
+    if (st) return st;
+    return hip_check(c, hipStreamSynchronize(c->stream), "download");
+}
+
+size_t elem(const lbfd_ctx* c) { return c->fp32 ? 4 : 8; }
+
+lbfd_status validate_grid(const lbfd_grid* g, std::string& msg) {
+    if (!g) return msg = "null grid", LBFD_E_INVAL;
+    if (g->dim != 2 && g->dim != 3) return msg = "dim must be 2 or 3", LBFD_E_INVAL;
+    if (g->nx < 2 || g->ny < 1 || g->nz < 1) return msg = "grid too small", LBFD_E_INVAL;
+    if (g->dim == 2 && g->nz != 1) return msg = "dim 2 needs nz == 1", LBFD_E_INVAL;
+    if (g->precision != LBFD_FP32 && g->precision != LBFD_FP64)
+        return msg = "unknown precision", LBFD_E_INVAL;
+    if (g->n_species < 0 || g->n_species > LBFD_MAX_SPECIES)
+        return msg = "n_species out of range", LBFD_E_INVAL;
+    const double N = (double)g->nx * g->ny * g->nz;
+    if (N * lattice_q(g->dim) > (double)INT_MAX) return msg = "grid too large", LBFD_E_INVAL;
+    const int nf = g->dim == 2 ? 4 : 6;
+    for (int f = 0; f < 6; ++f) {
+        const int lb = g->lb_bc[f], fd = g->fd_bc[f];
+        if (lb < 0 || lb > 3 || fd < 0 || fd > 2) return msg = "unknown boundary kind", LBFD_E_INVAL;
+        if (f >= nf && (lb != LBFD_LB_PERIODIC || fd != LBFD_FD_PERIODIC))
+            return msg = "z faces of a 2-D grid must be periodic", LBFD_E_INVAL;
+        if ((lb == LBFD_LB_PERIODIC) != (fd == LBFD_FD_PERIODIC))
+            return msg = "LB and FD must agree on periodic faces", LBFD_E_INVAL;
+        if (lb == LBFD_LB_VELOCITY_INLET && f != 0)
+            return msg = "velocity inlet only on the -x face", LBFD_E_UNSUPPORTED;
+        if (lb == LBFD_LB_PRESSURE_OUTLET && f != 1)
+            return msg = "pressure outlet only on the +x face", LBFD_E_UNSUPPORTED;
+    }
+    for (int a = 0; a < 3; ++a)
+        if ((g->lb_bc[2 * a] == LBFD_LB_PERIODIC) != (g->lb_bc[2 * a + 1] == LBFD_LB_PERIODIC))
+            return msg = "both faces of an axis must be periodic or neither", LBFD_E_INVAL;
+    return LBFD_OK;
+}
+
+template <typename R>
+lbfd_status launch_step(lbfd_ctx* c, int phase) {
+    StepArgs<R> a;
+    const size_t N = c->N;
+    a.g = dptr<R>(c, c->L.g);
+    a.T_cur = dptr<R>(c, c->cur ? c->L.T1 : c->L.T0);
+    a.T_nxt = dptr<R>(c, c->cur ? c->L.T0 : c->L.T1);
+    a.Y_cur = dptr<R>(c, c->cur ? c->L.Y1 : c->L.Y0);
+    a.Y_nxt = dptr<R>(c, c->cur ? c->L.Y0 : c->L.Y1);
+    a.divu = dptr<R>(c, c->L.divu);
+    a.phi = dptr<R>(c, c->L.phi);
+    a.partials = dptr<double>(c, c->L.part);
+    a.P = dptr<Par<R>>(c, sizeof(R) == 4 ? c->L.parf : c->L.pard);
+    a.PD = dptr<Par<double>>(c, c->L.pard);
+    a.N = (int)N;
+    a.nblocks = c->L.nblocks;
+    a.nbx = c->L.nbx;
+    a.nby = c->L.nby;
+    a.odd = c->odd;
+    a.phase = phase;
+    a.diag = 1;
+    hipError_t e;
+    if constexpr (sizeof(R) == 4)
+        e = launch_step_f32(c->dim, c->nsm, a, c->L.grid, c->stream);
+    else
+        e = launch_step_f64(c->dim, c->nsm, a, c->L.grid, c->stream);
+    return hip_check(c, e, "step kernel launch");
+}
+
+template <typename R>
+lbfd_status launch_macro(lbfd_ctx* c) {
+    MacroArgs<R> a;
+    const size_t N = c->N;
+    a.g = dptr<R>(c, c->L.g);
+    a.T = dptr<R>(c, c->cur ? c->L.T1 : c->L.T0);
+    a.Y = dptr<R>(c, c->cur ? c->L.Y1 : c->L.Y0);
+    a.divu = dptr<R>(c, c->L.divu);
+    a.phi = dptr<R>(c, c->L.phi);
+    a.out = dptr<double>(c, c->L.scratch);
+    a.P = dptr<Par<R>>(c, sizeof(R) == 4 ? c->L.parf : c->L.pard);
+    a.PD = dptr<Par<double>>(c, c->L.pard);
+    a.N = (int)N;
+    a.nblocks = c->L.nlin;
+    a.odd = c->odd;
+    hipError_t e;
+    if constexpr (sizeof(R) == 4)
+        e = launch_macro_f32(c->dim, c->nsm, a, c->L.nlin, c->stream);
+    else
+        e = launch_macro_f64(c->dim, c->nsm, a, c->L.nlin, c->stream);
+    return hip_check(c, e, "read kernel launch");
+}
+
+template <typename R>
+lbfd_status launch_init(lbfd_ctx* c, bool with_u) {
+    InitArgs<R> a;
+    a.g = dptr<R>(c, c->L.g);
+    a.T = dptr<R>(c, c->L.T0);
+    a.Y = dptr<R>(c, c->L.Y0);
+    a.u = with_u ? dptr<double>(c, c->L.scratch) : nullptr;
+    a.divu = dptr<R>(c, c->L.divu);
+    a.P = dptr<Par<R>>(c, sizeof(R) == 4 ? c->L.parf : c->L.pard);
+    a.N = (int)c->N;
+    hipError_t e;
+    if constexpr (sizeof(R) == 4)
+        e = launch_init_f32(c->dim, c->nsm, a, c->L.nlin, c->stream);
+    else
+        e = launch_init_f64(c->dim, c->nsm, a, c->L.nlin, c->stream);
+    return hip_check(c, e, "init kernel launch");
+}
+
+lbfd_status set_device(lbfd_ctx* c) { return hip_check(c, hipSetDevice(c->device), "hipSetDevice"); }
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+lbfd_status lbfd_workspace_bytes(const lbfd_grid* grid, size_t* bytes) {
+    std::string msg;
+    lbfd_status st = validate_grid(grid, msg);
+    if (st) return st;
+    if (!bytes) return LBFD_E_INVAL;
+    *bytes = make_layout(*grid).total;
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_create(const lbfd_grid* grid, void* dev_workspace, size_t bytes, void* hip_stream,
+                        lbfd_ctx** out) {
+    if (!out) return LBFD_E_INVAL;
+    *out = nullptr;
+    std::string msg;
+    lbfd_status st = validate_grid(grid, msg);
+    if (st) return st;
+    Layout L = make_layout(*grid);
+    if (!dev_workspace) return LBFD_E_INVAL;
+    if (bytes < L.total) return LBFD_E_NOMEM;
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0) return LBFD_E_INVAL;
+    lbfd_ctx* c = new (std::nothrow) lbfd_ctx();
+    if (!c) return LBFD_E_NOMEM;
+    c->grid = *grid;
+    c->L = L;
+    c->dim = grid->dim;
+    c->Q = lattice_q(grid->dim);
+    c->ns = grid->n_species;
+    c->nsm = nsm_bucket(c->ns);
+    c->N = (size_t)grid->nx * grid->ny * grid->nz;
+    c->fp32 = grid->precision == LBFD_FP32;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->ws = reinterpret_cast<char*>(dev_workspace);
+    std::memset(&c->params, 0, sizeof(c->params));
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return LBFD_E_DEVICE;
+    }
+    *out = c;
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_set_phase_field(lbfd_ctx* c, const double* phi) {
+    if (!c || !phi) return LBFD_E_INVAL;
+    for (size_t i = 0; i < c->N; ++i)
+        if (!(phi[i] >= 0.0 && phi[i] <= 1.0))
+            return fail(c, LBFD_E_INVAL, "phase field outside [0, 1]");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    st = upload_field(c, c->L.phi, phi, c->N);
+    if (st) return st;
+    c->have_phi = true;
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_set_mechanism(lbfd_ctx* c, const lbfd_mechanism* m) {
+    if (!c || !m) return LBFD_E_INVAL;
+    if (m->n_species != c->ns) return fail(c, LBFD_E_INVAL, "mechanism species != grid species");
+    if (m->n_reactions < 0 || m->n_reactions > LBFD_MAX_REACTIONS)
+        return fail(c, LBFD_E_INVAL, "n_reactions out of range");
+    const int ns = c->ns, nr = m->n_reactions;
+    if (ns > 0 && (!m->M || !m->dhf || !m->mu_star)) return fail(c, LBFD_E_INVAL, "null table");
+    if (nr > 0 && (!m->nu_f || !m->nu_r || !m->A || !m->beta || !m->theta || !m->reversible ||
+                   !m->lnKc_a || !m->lnKc_b))
+        return fail(c, LBFD_E_INVAL, "null table");
+    HostMech h;
+    h.ns = ns;
+    h.nr = nr;
+    for (int k = 0; k < ns; ++k) {
+        if (!(m->M[k] > 0.0) || !(m->mu_star[k] > 0.0) || !std::isfinite(m->dhf[k]))
+            return fail(c, LBFD_E_INVAL, "bad species data");
+        h.M.push_back(m->M[k]);
+        h.dhf.push_back(m->dhf[k]);
+        h.mu_star.push_back(m->mu_star[k]);
+    }
+    for (int j = 0; j < nr; ++j) {
+        if (!(m->A[j] >= 0.0) || !std::isfinite(m->beta[j]) || !std::isfinite(m->theta[j]) ||
+            !std::isfinite(m->lnKc_a[j]) || !std::isfinite(m->lnKc_b[j]))
+            return fail(c, LBFD_E_INVAL, "bad rate data");
+        h.A.push_back(m->A[j]);
+        h.beta.push_back(m->beta[j]);
+        h.theta.push_back(m->theta[j]);
+        h.lnKc_a.push_back(m->lnKc_a[j]);
+        h.lnKc_b.push_back(m->lnKc_b[j]);
+        h.rev.push_back(m->reversible[j] ? 1 : 0);
+        for (int k = 0; k < ns; ++k) {
+            const int f = m->nu_f[j * ns + k], r = m->nu_r[j * ns + k];
+            if (f < 0 || f > 3 || r < 0 || r > 3)
+                return fail(c, LBFD_E_INVAL, "stoichiometric coefficients must be 0..3");
+            h.nu_f.push_back(f);
+            h.nu_r.push_back(r);
+        }
+    }
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    HostMech old = c->mech;
+    bool had = c->have_mech;
+    c->mech = h;
+    c->have_mech = true;
+    st = upload_tables(c);
+    if (st) {
+        c->mech = old;
+        c->have_mech = had;
+        return st;
+    }
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_set_params(lbfd_ctx* c, const lbfd_params* p) {
+    if (!c || !p) return LBFD_E_INVAL;
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(p->eta) || !pos(p->cp) || !pos(p->Pr) || !pos(p->rho_in) || !pos(p->T_in) ||
+        !pos(p->nu_in) || !pos(p->T_solid) || !(p->sutherland_S >= 0.0))
+        return fail(c, LBFD_E_INVAL, "eta, cp, Pr, rho_in, T_in, nu_in, T_solid must be positive");
+    if (!(p->A_u >= 0.0) || !(p->A_T >= 0.0)) return fail(c, LBFD_E_INVAL, "negative coupling");
+    if (p->mu_model != 0 && p->mu_model != 1) return fail(c, LBFD_E_INVAL, "mu_model");
+    if (p->transport_model != 0 && p->transport_model != 1)
+        return fail(c, LBFD_E_INVAL, "transport_model");
+    if (p->n_sub < 1 || p->n_sub > 4096) return fail(c, LBFD_E_INVAL, "n_sub must be 1..4096");
+    const double tau_in = p->nu_in * 3.0 + 0.5;
+    if (!(tau_in > 0.5 + 1e-3)) return fail(c, LBFD_E_INVAL, "relaxation time at the inlet <= 0.501");
+    const double uin = std::sqrt(p->u_in[0] * p->u_in[0] + p->u_in[1] * p->u_in[1] +
+                                 p->u_in[2] * p->u_in[2]);
+    if (!(uin <= 0.1)) return fail(c, LBFD_E_INVAL, "|u_in| > 0.1 (low-Mach limit)");
+    double im = 0.0;
+    for (int k = 0; k < c->ns; ++k) {
+        if (!pos(p->Le[k])) return fail(c, LBFD_E_INVAL, "Lewis numbers must be positive");
+        if (!(p->Y_in[k] >= 0.0)) return fail(c, LBFD_E_INVAL, "negative inlet mass fraction");
+        im += p->Y_in[k];
+    }
+    if (c->ns > 0 && !(std::fabs(im - 1.0) < 1e-6))
+        return fail(c, LBFD_E_INVAL, "inlet mass fractions must sum to 1");
+    for (int f = 0; f < 6; ++f)
+        if (c->grid.fd_bc[f] == LBFD_FD_DIRICHLET && !pos(p->fd_face[f][0]))
+            return fail(c, LBFD_E_INVAL, "Dirichlet face temperature must be positive");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    lbfd_params old = c->params;
+    bool had = c->have_params;
+    c->params = *p;
+    c->have_params = true;
+    st = upload_tables(c);
+    if (st) {
+        c->params = old;
+        c->have_params = had;
+        return st;
+    }
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const double* u) {
+    if (!c || !T) return LBFD_E_INVAL;
+    if (c->ns > 0 && !Y) return fail(c, LBFD_E_INVAL, "Y required when n_species > 0");
+    if (!c->have_phi || !ready_for_tables(c))
+        return fail(c, LBFD_E_STATE, "phase field, params (and mechanism) must be set first");
+    for (size_t i = 0; i < c->N; ++i)
+        if (!(T[i] > 0.0) || !std::isfinite(T[i]))
+            return fail(c, LBFD_E_INVAL, "temperature must be positive and finite");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    if ((st = upload_field(c, c->L.T0, T, c->N))) return st;
+    if (c->ns > 0 && (st = upload_field(c, c->L.Y0, Y, (size_t)c->ns * c->N))) return st;
+    if (u) {
+        st = hip_check(c, hipMemcpyAsync(dptr<char>(c, c->L.scratch), u, c->dim * c->N * 8,
+                                         hipMemcpyHostToDevice, c->stream),
+                       "upload u");
+        if (st) return st;
+    }
+    st = c->fp32 ? launch_init<float>(c, u != nullptr) : launch_init<double>(c, u != nullptr);
+    if (st) return st;
+    st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.part), 0,
+                                     (size_t)c->L.nblocks * DIAG_STRIDE * sizeof(double), c->stream),
+                   "clear diagnostics");
+    if (st) return st;
+    st = hip_check(c, hipStreamSynchronize(c->stream), "init");
+    if (st) return st;
+    c->cur = 0;
+    c->odd = 0;
+    c->steps = 0;
+    c->have_state = true;
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_set_populations(lbfd_ctx* c, const double* g, const double* divu) {
+    if (!c || !g) return LBFD_E_INVAL;
+    if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    if ((st = upload_field(c, c->L.g, g, (size_t)c->Q * c->N))) return st;
+    if (divu && (st = upload_field(c, c->L.divu, divu, c->N))) return st;
+    c->odd = 0;
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_step_phase(lbfd_ctx* c, int32_t n, int32_t phase) {
+    if (!c || n < 0 || phase < 0 || phase > 7) return LBFD_E_INVAL;
+    if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    for (int i = 0; i < n; ++i) {
+        st = c->fp32 ? launch_step<float>(c, phase) : launch_step<double>(c, phase);
+        if (st) return st;
+        c->cur ^= 1;
+        if (phase & PH_LB) c->odd ^= 1;
+        c->steps++;
+    }
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_step(lbfd_ctx* c, int32_t n) { return lbfd_step_phase(c, n, LBFD_PHASE_ALL); }
+
+lbfd_status lbfd_read(lbfd_ctx* c, int32_t field, int32_t comp, double* out) {
+    if (!c || !out) return LBFD_E_INVAL;
+    if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    const size_t N = c->N, s = elem(c);
+    switch (field) {
+    case LBFD_F_T:
+        return download_field(c, c->cur ? c->L.T1 : c->L.T0, out, N);
+    case LBFD_F_Y:
+        if (comp < 0 || comp >= c->ns) return fail(c, LBFD_E_INVAL, "species index");
+        return download_field(c, (c->cur ? c->L.Y1 : c->L.Y0) + comp * N * s, out, N);
+    case LBFD_F_DIVU:
+        return download_field(c, c->L.divu, out, N);
+    case LBFD_F_POPULATIONS: {
+        if (comp < 0 || comp >= c->Q) return fail(c, LBFD_E_INVAL, "population index");
+        if (!c->odd) return download_field(c, c->L.g + comp * N * s, out, N);
+        // swapped AA layout: natural g_i(x) sits in slot opp(i) of x - c_i, or
+        // in the cell's own slot i when x - c_i is outside the domain
+        std::vector<double> own(N), nb(N);
+        const int i = comp, j = opp(comp);
+        if ((st = download_field(c, c->L.g + i * N * s, own.data(), N))) return st;
+        if ((st = download_field(c, c->L.g + j * N * s, nb.data(), N))) return st;
+        const int* cx = c->dim == 2 ? Lat<2>::cx : Lat<3>::cx;
+        const int* cy = c->dim == 2 ? Lat<2>::cy : Lat<3>::cy;
+        const int* cz = c->dim == 2 ? Lat<2>::cz : Lat<3>::cz;
+        const int n[3] = {c->grid.nx, c->grid.ny, c->grid.nz};
+        for (int z = 0; z < n[2]; ++z)
+            for (int y = 0; y < n[1]; ++y)
+                for (int x = 0; x < n[0]; ++x) {
+                    int p[3] = {x - cx[i], y - cy[i], z - cz[i]};
+                    bool inside = true;
+                    for (int a = 0; a < 3; ++a) {
+                        if (p[a] >= 0 && p[a] < n[a]) continue;
+                        if (c->grid.lb_bc[2 * a] == LBFD_LB_PERIODIC)
+                            p[a] = (p[a] + n[a]) % n[a];
+                        else
+                            inside = false;
+                    }
+                    const size_t id = ((size_t)z * n[1] + y) * n[0] + x;
+                    out[id] = inside ? nb[((size_t)p[2] * n[1] + p[1]) * n[0] + p[0]] : own[id];
+                }
+        return LBFD_OK;
+    }
+    case LBFD_F_RHO:
+    case LBFD_F_U:
+    case LBFD_F_PH: {
+        if (field == LBFD_F_U && (comp < 0 || comp >= c->dim))
+            return fail(c, LBFD_E_INVAL, "velocity component");
+        st = c->fp32 ? launch_macro<float>(c) : launch_macro<double>(c);
+        if (st) return st;
+        const int slot = field == LBFD_F_RHO ? 0 : field == LBFD_F_U ? 1 + comp : 4;
+        st = hip_check(c, hipMemcpyAsync(out, dptr<double>(c, c->L.scratch) + slot * N, N * 8,
+                                         hipMemcpyDeviceToHost, c->stream),
+                       "read");
+        if (st) return st;
+        return hip_check(c, hipStreamSynchronize(c->stream), "read");
+    }
+    default:
+        return fail(c, LBFD_E_INVAL, "unknown field");
+    }
+}
+
+lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
+    if (!c || !out) return LBFD_E_INVAL;
+    if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    double* red = dptr<double>(c, c->L.red);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(BLOCK), 0, c->stream,
+                       dptr<double>(c, c->L.part), c->L.nblocks, c->ns, red);
+    if ((st = hip_check(c, hipGetLastError(), "diagnostics launch"))) return st;
+    double h[DG_COUNT];
+    st = hip_check(c, hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, c->stream),
+                   "diagnostics");
+    if (st) return st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "diagnostics"))) return st;
+    std::memset(out, 0, sizeof(*out));
+    out->mass = h[DG_MASS];
+    for (int k = 0; k < c->ns; ++k) out->species_mass[k] = h[DG_SP + k];
+    out->enthalpy = h[DG_ENTH];
+    out->kinetic = h[DG_KIN];
+    out->umax = h[DG_UMAX];
+    out->Tmin = h[DG_TMIN];
+    out->Tmax = h[DG_TMAX];
+    out->n_nonfinite = (int64_t)h[DG_NONFIN];
+    out->n_tau_bad = (int64_t)h[DG_TAUBAD];
+    out->n_negY = (int64_t)h[DG_NEGY];
+    out->n_flagged_fp64 = (int64_t)h[DG_FLAG];
+    out->n_fallback = (int64_t)h[DG_FALLBACK];
+    out->step = c->steps;
+    if (out->n_nonfinite > 0) return fail(c, LBFD_E_NUMERIC, "non-finite values in the state");
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_synchronize(lbfd_ctx* c) {
+    if (!c) return LBFD_E_INVAL;
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    return hip_check(c, hipStreamSynchronize(c->stream), "synchronize");
+}
+
+lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* c, double* bytes) {
+    if (!c || !bytes) return LBFD_E_INVAL;
+    // populations read+write, T and Y read+write, divu read+write, phi read
+    *bytes = (double)elem(c) * (2.0 * c->Q + 2.0 + 2.0 * c->ns + 2.0 + 1.0);
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_destroy(lbfd_ctx* c) {
+    delete c;
+    return LBFD_OK;
+}
+
+const char* lbfd_last_error(const lbfd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

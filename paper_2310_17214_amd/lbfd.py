@@ -1,0 +1,268 @@
+"""Python binding of the C ABI in include/lbfd.h (liblbfd_hip.so).
+
+Argument marshalling only: every step of the coupled update runs in the HIP
+kernels of the library.  PyTorch provides the device workspace (a uint8 CUDA
+tensor) and the stream.  The library is loaded from the package directory;
+if it has not been built, importing this module fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbfd_hip.so")
+MAX_SPECIES, MAX_REACTIONS = 16, 32
+
+LBFD_OK, LBFD_E_INVAL, LBFD_E_NOMEM, LBFD_E_DEVICE = 0, -1, -2, -3
+LBFD_E_STATE, LBFD_E_NUMERIC, LBFD_E_UNSUPPORTED = -4, -5, -6
+STATUS = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_STATE",
+          -5: "E_NUMERIC", -6: "E_UNSUPPORTED"}
+FP64, FP32 = 0, 1
+F_RHO, F_U, F_T, F_Y, F_PH, F_POPULATIONS, F_DIVU = range(7)
+PHASE_LB, PHASE_FD, PHASE_CHEM, PHASE_ALL = 1, 2, 4, 7
+LB_BC = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
+FD_BC = {"periodic": 0, "dirichlet": 1, "neumann": 2}
+
+EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd_set_mechanism",
+            "lbfd_set_params", "lbfd_init_state", "lbfd_set_populations", "lbfd_step",
+            "lbfd_step_phase", "lbfd_read", "lbfd_diagnostics", "lbfd_synchronize",
+            "lbfd_step_bytes_per_cell", "lbfd_destroy", "lbfd_last_error"]
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("precision", C.c_int32), ("n_species", C.c_int32),
+                ("lb_bc", C.c_int32 * 6), ("fd_bc", C.c_int32 * 6)]
+
+
+class Params(C.Structure):
+    _fields_ = [("A_u", C.c_double), ("A_T", C.c_double), ("eta", C.c_double),
+                ("T_solid", C.c_double), ("Pr", C.c_double), ("cp", C.c_double),
+                ("rho_in", C.c_double), ("T_in", C.c_double), ("nu_in", C.c_double),
+                ("sutherland_S", C.c_double), ("mu_model", C.c_int32),
+                ("transport_model", C.c_int32), ("u_in", C.c_double * 3),
+                ("body_force", C.c_double * 3), ("Y_in", C.c_double * MAX_SPECIES),
+                ("Le", C.c_double * MAX_SPECIES),
+                ("fd_face", (C.c_double * (1 + MAX_SPECIES)) * 6),
+                ("n_sub", C.c_int32), ("ign_threshold", C.c_double)]
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class Mechanism(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("M", _dp), ("dhf", _dp), ("mu_star", _dp), ("nu_f", _ip), ("nu_r", _ip),
+                ("A", _dp), ("beta", _dp), ("theta", _dp), ("reversible", _ip),
+                ("lnKc_a", _dp), ("lnKc_b", _dp)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("mass", C.c_double), ("species_mass", C.c_double * MAX_SPECIES),
+                ("enthalpy", C.c_double), ("kinetic", C.c_double), ("umax", C.c_double),
+                ("Tmin", C.c_double), ("Tmax", C.c_double), ("n_nonfinite", C.c_int64),
+                ("n_tau_bad", C.c_int64), ("n_negY", C.c_int64), ("n_flagged_fp64", C.c_int64),
+                ("n_fallback", C.c_int64), ("step", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbfd_hip.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, st = C.c_void_p, C.c_int
+        L.lbfd_workspace_bytes.argtypes = [C.POINTER(Grid), C.POINTER(C.c_size_t)]
+        L.lbfd_create.argtypes = [C.POINTER(Grid), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbfd_set_phase_field.argtypes = [vp, _dp]
+        L.lbfd_set_mechanism.argtypes = [vp, C.POINTER(Mechanism)]
+        L.lbfd_set_params.argtypes = [vp, C.POINTER(Params)]
+        L.lbfd_init_state.argtypes = [vp, _dp, _dp, _dp]
+        L.lbfd_set_populations.argtypes = [vp, _dp, _dp]
+        L.lbfd_step.argtypes = [vp, C.c_int32]
+        L.lbfd_step_phase.argtypes = [vp, C.c_int32, C.c_int32]
+        L.lbfd_read.argtypes = [vp, C.c_int32, C.c_int32, _dp]
+        L.lbfd_diagnostics.argtypes = [vp, C.POINTER(Diag)]
+        L.lbfd_synchronize.argtypes = [vp]
+        L.lbfd_step_bytes_per_cell.argtypes = [vp, _dp]
+        L.lbfd_destroy.argtypes = [vp]
+        L.lbfd_last_error.argtypes = [vp]
+        L.lbfd_last_error.restype = C.c_char_p
+        for name in EXPORTED:
+            if name != "lbfd_last_error":
+                getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+class LbfdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def make_grid(s: dict) -> Grid:
+    g = Grid()
+    g.dim, g.nx, g.ny, g.nz = s["dim"], s["nx"], s["ny"], s["nz"]
+    g.precision = FP32 if s.get("precision", "fp64") == "fp32" else FP64
+    g.n_species = s["ns"]
+    for f in range(6):
+        g.lb_bc[f] = LB_BC[s["lb_bc"][f]]
+        g.fd_bc[f] = FD_BC[s["fd_bc"][f]]
+    return g
+
+
+def make_params(s: dict) -> Params:
+    p = Params()
+    p.A_u, p.A_T, p.eta, p.T_solid = s["A_u"], s["A_T"], s["eta"], s["T_s"]
+    p.Pr, p.cp, p.rho_in, p.T_in = s["Pr"], s["cp"], s["rho_in"], s["T_in"]
+    p.nu_in, p.sutherland_S = s["nu_in"], s["S_suth"]
+    p.mu_model, p.transport_model = s["mu_model"], s["transport"]
+    for a in range(3):
+        p.u_in[a] = s["u_in"][a]
+        p.body_force[a] = s["F_b"][a]
+    for k in range(s["ns"]):
+        p.Y_in[k] = s["Y_in"][k]
+        p.Le[k] = s["Le"][k]
+    for f in range(6):
+        for j, v in enumerate(s["fd_val"][f]):
+            p.fd_face[f][j] = v
+    p.n_sub, p.ign_threshold = s["n_sub"], s["theta_ign"]
+    return p
+
+
+class _MechArrays:
+    """Keeps the numpy tables alive while the struct points at them."""
+
+    def __init__(self, s: dict):
+        m, ns = s["mech"], s["ns"]
+        nr = len(m["A"])
+        f64 = lambda v, n: np.ascontiguousarray(np.resize(np.asarray(v, np.float64), max(n, 1)))
+        i32 = lambda v, n: np.ascontiguousarray(np.resize(np.asarray(v, np.int32).reshape(-1),
+                                                          max(n, 1)))
+        self.arrs = dict(M=f64(m["M"], ns), dhf=f64(m["dhf"], ns), mu_star=f64(m["mu_star"], ns),
+                         nu_f=i32(m["nu_f"] if nr else [0], nr * ns),
+                         nu_r=i32(m["nu_r"] if nr else [0], nr * ns),
+                         A=f64(m["A"] if nr else [0], nr), beta=f64(m["beta"] if nr else [0], nr),
+                         theta=f64(m["theta"] if nr else [0], nr),
+                         reversible=i32(m["rev"] if nr else [0], nr),
+                         lnKc_a=f64(m["lnKc_a"] if nr else [0], nr),
+                         lnKc_b=f64(m["lnKc_b"] if nr else [0], nr))
+        st = Mechanism()
+        st.n_species, st.n_reactions = ns, nr
+        for k, a in self.arrs.items():
+            setattr(st, k, a.ctypes.data_as(_ip if a.dtype == np.int32 else _dp))
+        self.struct = st
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+
+
+class Context:
+    """One simulation on one GPU: owns a torch workspace and a C context."""
+
+    def __init__(self, setup: dict, phi: np.ndarray, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible")
+        L = lib()
+        self.setup = setup
+        self.dim, self.ns = setup["dim"], setup["ns"]
+        self.Q = 9 if self.dim == 2 else 19
+        self.shape = (setup["nz"], setup["ny"], setup["nx"])
+        self.N = int(np.prod(self.shape))
+        self._grid = make_grid(setup)
+        nbytes = C.c_size_t()
+        self._check(L.lbfd_workspace_bytes(C.byref(self._grid), C.byref(nbytes)), None)
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        self._ptr = base + (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        self._check(L.lbfd_create(C.byref(self._grid), C.c_void_p(self._ptr), nbytes.value,
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
+        self._h = h
+        self._check(L.lbfd_set_phase_field(h, _f64(phi).ctypes.data_as(_dp)))
+        if self.ns > 0:
+            self._mech = _MechArrays(setup)
+            self._check(L.lbfd_set_mechanism(h, C.byref(self._mech.struct)))
+        self._params = make_params(setup)
+        self._check(L.lbfd_set_params(h, C.byref(self._params)))
+
+    def _check(self, status, h="self"):
+        if status != LBFD_OK:
+            handle = self._h if h == "self" else None
+            msg = lib().lbfd_last_error(handle).decode() if handle else ""
+            raise LbfdError(status, msg)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                lib().lbfd_synchronize(h)
+            finally:
+                lib().lbfd_destroy(h)
+            self._h = None
+
+    def init_state(self, T, Y=None, u=None):
+        T = _f64(T)
+        Yb = _f64(Y) if (Y is not None and self.ns) else None
+        ub = _f64(u) if u is not None else None
+        self._check(lib().lbfd_init_state(self._h, T.ctypes.data_as(_dp),
+                                          None if Yb is None else Yb.ctypes.data_as(_dp),
+                                          None if ub is None else ub.ctypes.data_as(_dp)))
+
+    def set_populations(self, g, divu=None):
+        g = _f64(g)
+        d = _f64(divu) if divu is not None else None
+        self._check(lib().lbfd_set_populations(self._h, g.ctypes.data_as(_dp),
+                                               None if d is None else d.ctypes.data_as(_dp)))
+
+    def step(self, n=1):
+        self._check(lib().lbfd_step(self._h, int(n)))
+
+    def step_phase(self, n, mask):
+        self._check(lib().lbfd_step_phase(self._h, int(n), int(mask)))
+
+    def synchronize(self):
+        self._check(lib().lbfd_synchronize(self._h))
+
+    def read(self, field, comp=0):
+        out = np.empty(self.N, np.float64)
+        self._check(lib().lbfd_read(self._h, int(field), int(comp), out.ctypes.data_as(_dp)))
+        return out.reshape(self.shape)
+
+    def fields(self):
+        d = {"rho": self.read(F_RHO), "T": self.read(F_T), "Ph": self.read(F_PH),
+             "divu": self.read(F_DIVU)}
+        d["u"] = np.stack([self.read(F_U, a) for a in range(self.dim)])
+        if self.ns:
+            d["Y"] = np.stack([self.read(F_Y, k) for k in range(self.ns)])
+        return d
+
+    def populations(self):
+        return np.stack([self.read(F_POPULATIONS, i) for i in range(self.Q)])
+
+    def diagnostics(self, allow_numeric=False):
+        d = Diag()
+        st = lib().lbfd_diagnostics(self._h, C.byref(d))
+        if st != LBFD_OK and not (allow_numeric and st == LBFD_E_NUMERIC):
+            self._check(st)
+        out = {k: getattr(d, k) for k, _ in Diag._fields_ if k != "species_mass"}
+        out["species_mass"] = np.array(d.species_mass[: self.ns])
+        out["status"] = st
+        return out
+
+    def bytes_per_cell(self):
+        b = C.c_double()
+        self._check(lib().lbfd_step_bytes_per_cell(self._h, C.byref(b)))
+        return b.value
