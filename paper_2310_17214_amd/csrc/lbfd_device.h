@@ -234,11 +234,13 @@ struct StepArgs {
     R* divu;              // [N] (read, then overwritten in place)
     const R* phi;         // [N] solid fraction
     double* partials;     // [nblocks][DIAG_STRIDE]
+    unsigned long long* flags;  // [nblocks][zc][waves] reaction-active cells (FP32 mode)
     const Par<R>* P;
     const Par<double>* PD;
     int N;
     int nblocks;          // real workgroups (grid may be padded to a multiple of 8)
-    int nbx, nby;         // 64 x 4 cell tiles along x and y
+    int nbx, nby;         // cell tiles along x and y
+    int zc;               // planes per workgroup (z-march length)
     int odd;              // AA parity of this step
     int phase;            // PH_* mask
     int diag;             // write diagnostics partials

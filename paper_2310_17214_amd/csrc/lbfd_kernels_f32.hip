@@ -29,4 +29,21 @@ hipError_t launch_init_f32(int dim, int nsm, const InitArgs<float>& a, int grid,
     default: return launch_init_t<float, 16>(dim, a, grid, s);
     }
 }
+
+int step_tile_h_f32(int dim, int nsm) {
+    switch (nsm) {
+    case 0: return tile_h_t<float, 0>(dim);
+    case 4: return tile_h_t<float, 4>(dim);
+    case 9: return tile_h_t<float, 9>(dim);
+    default: return tile_h_t<float, 16>(dim);
+    }
+}
+hipError_t launch_island_f32(int dim, int nsm, const StepArgs<float>& a, int grid, hipStream_t s) {
+    switch (nsm) {
+    case 0: return hipSuccess;
+    case 4: return launch_island_t<4>(dim, a, grid, s);
+    case 9: return launch_island_t<9>(dim, a, grid, s);
+    default: return launch_island_t<16>(dim, a, grid, s);
+    }
+}
 }  // namespace lbfd

@@ -29,4 +29,13 @@ hipError_t launch_init_f64(int dim, int nsm, const InitArgs<double>& a, int grid
     default: return launch_init_t<double, 16>(dim, a, grid, s);
     }
 }
+
+int step_tile_h_f64(int dim, int nsm) {
+    switch (nsm) {
+    case 0: return tile_h_t<double, 0>(dim);
+    case 4: return tile_h_t<double, 4>(dim);
+    case 9: return tile_h_t<double, 9>(dim);
+    default: return tile_h_t<double, 16>(dim);
+    }
+}
 }  // namespace lbfd

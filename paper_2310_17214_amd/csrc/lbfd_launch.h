@@ -12,4 +12,8 @@ hipError_t launch_macro_f32(int dim, int nsm, const MacroArgs<float>& a, int gri
 hipError_t launch_macro_f64(int dim, int nsm, const MacroArgs<double>& a, int grid, hipStream_t s);
 hipError_t launch_init_f32(int dim, int nsm, const InitArgs<float>& a, int grid, hipStream_t s);
 hipError_t launch_init_f64(int dim, int nsm, const InitArgs<double>& a, int grid, hipStream_t s);
+hipError_t launch_island_f32(int dim, int nsm, const StepArgs<float>& a, int grid, hipStream_t s);
+// cell rows per workgroup tile of the step kernel (tiles are 32 cells wide)
+int step_tile_h_f32(int dim, int nsm);
+int step_tile_h_f64(int dim, int nsm);
 }  // namespace lbfd

@@ -3,6 +3,7 @@
 // caller's stream, field reads and the deterministic diagnostics reduction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -27,20 +28,27 @@ struct HostMech {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, T0, T1, Y0, Y1, divu, phi, part, parf, pard, scratch, red, total;
-    int nbx, nby, nblocks, grid;  // step kernel: 64 x 4 tiles, grid padded to 8 XCDs
+    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, parf, pard, scratch, red, total;
+    int nbx, nby, zc, nblocks, grid;  // step kernel: 32 x 8 tiles marching zc planes,
+                                      // grid padded to a multiple of the 8 XCDs
     int nlin;                     // one-cell-per-thread kernels
 };
 
 int lattice_q(int dim) { return dim == 2 ? 9 : 19; }
+int nsm_bucket(int ns) { return ns == 0 ? 0 : ns <= 4 ? 4 : ns <= 9 ? 9 : 16; }
 
 Layout make_layout(const lbfd_grid& gr) {
     Layout L;
     const size_t N = (size_t)gr.nx * gr.ny * gr.nz;
     const size_t s = gr.precision == LBFD_FP32 ? 4 : 8;
     const int Q = lattice_q(gr.dim);
-    L.nbx = (gr.nx + 63) / 64;
-    L.nby = (gr.ny + 3) / 4;
+    const int nsm = nsm_bucket(gr.n_species);
+    const int th = gr.precision == LBFD_FP32 ? step_tile_h_f32(gr.dim, nsm)
+                                             : step_tile_h_f64(gr.dim, nsm);
+    const int tw = BLOCK / th;
+    L.nbx = (gr.nx + tw - 1) / tw;
+    L.nby = (gr.ny + th - 1) / th;
+    L.zc = 1;
     L.nblocks = L.nbx * L.nby * gr.nz;
     L.grid = (L.nblocks + 7) / 8 * 8;
     L.nlin = (int)((N + BLOCK - 1) / BLOCK);
@@ -53,11 +61,13 @@ Layout make_layout(const lbfd_grid& gr) {
     L.g = take(Q * N * s);
     L.T0 = take(N * s);
     L.T1 = take(N * s);
-    L.Y0 = take((size_t)gr.n_species * N * s);
-    L.Y1 = take((size_t)gr.n_species * N * s);
+    // species planes for the kernel's species bucket (planes past n_species stay zero)
+    L.Y0 = take((size_t)nsm_bucket(gr.n_species) * N * s);
+    L.Y1 = take((size_t)nsm_bucket(gr.n_species) * N * s);
     L.divu = take(N * s);
     L.phi = take(N * s);
     L.part = take((size_t)L.nblocks * DIAG_STRIDE * sizeof(double));
+    L.flags = take((size_t)L.nblocks * (BLOCK / 64) * sizeof(unsigned long long));
     L.parf = take(sizeof(Par<float>));
     L.pard = take(sizeof(Par<double>));
     L.scratch = take(5 * N * sizeof(double));
@@ -65,8 +75,6 @@ Layout make_layout(const lbfd_grid& gr) {
     L.total = off;
     return L;
 }
-
-int nsm_bucket(int ns) { return ns == 0 ? 0 : ns <= 4 ? 4 : ns <= 9 ? 9 : 16; }
 
 __global__ void reduce_partials(const double* __restrict__ part, int nblocks, int ns,
                                 double* __restrict__ out) {
@@ -309,20 +317,25 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.divu = dptr<R>(c, c->L.divu);
     a.phi = dptr<R>(c, c->L.phi);
     a.partials = dptr<double>(c, c->L.part);
+    a.flags = dptr<unsigned long long>(c, c->L.flags);
     a.P = dptr<Par<R>>(c, sizeof(R) == 4 ? c->L.parf : c->L.pard);
     a.PD = dptr<Par<double>>(c, c->L.pard);
     a.N = (int)N;
     a.nblocks = c->L.nblocks;
     a.nbx = c->L.nbx;
     a.nby = c->L.nby;
+    a.zc = c->L.zc;
     a.odd = c->odd;
     a.phase = phase;
     a.diag = 1;
     hipError_t e;
-    if constexpr (sizeof(R) == 4)
+    if constexpr (sizeof(R) == 4) {
         e = launch_step_f32(c->dim, c->nsm, a, c->L.grid, c->stream);
-    else
+        if (e == hipSuccess && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM))
+            e = launch_island_f32(c->dim, c->nsm, a, c->L.grid, c->stream);
+    } else {
         e = launch_step_f64(c->dim, c->nsm, a, c->L.grid, c->stream);
+    }
     return hip_check(c, e, "step kernel launch");
 }
 
@@ -536,6 +549,13 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
     if (st) return st;
     if ((st = upload_field(c, c->L.T0, T, c->N))) return st;
     if (c->ns > 0 && (st = upload_field(c, c->L.Y0, Y, (size_t)c->ns * c->N))) return st;
+    if (c->nsm > c->ns) {  // padded species planes of the kernel's bucket
+        const size_t off = (size_t)c->ns * c->N * elem(c), len = (size_t)(c->nsm - c->ns) * c->N * elem(c);
+        if ((st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.Y0) + off, 0, len, c->stream), "clear")))
+            return st;
+        if ((st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.Y1) + off, 0, len, c->stream), "clear")))
+            return st;
+    }
     if (u) {
         st = hip_check(c, hipMemcpyAsync(dptr<char>(c, c->L.scratch), u, c->dim * c->N * 8,
                                          hipMemcpyHostToDevice, c->stream),
@@ -690,7 +710,7 @@ lbfd_status lbfd_synchronize(lbfd_ctx* c) {
 lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* c, double* bytes) {
     if (!c || !bytes) return LBFD_E_INVAL;
     // populations read+write, T and Y read+write, divu read+write, phi read
-    *bytes = (double)elem(c) * (2.0 * c->Q + 2.0 + 2.0 * c->ns + 2.0 + 1.0);
+    *bytes = (double)elem(c) * (2.0 * c->Q + 2.0 + 2.0 * c->nsm + 2.0 + 1.0);
     return LBFD_OK;
 }
 

@@ -30,6 +30,7 @@ MAX_REACTIONS = 32
 
 T_IN = 300.0
 A_U = 145.0  # optimal momentum coupling, Sec. 4.1
+THETA_IGN_BED = 1.0  # [K per step] FP64 reaction island threshold of the bed workloads
 
 
 def a_t_fit(t_wall: float, t_inlet: float = T_IN) -> float:
@@ -452,6 +453,9 @@ def _reactive_bed_setup(dim, nx, ny, nz, mech, Y_in, precision, T_s, nu_in, u_in
     s["transport"] = transport
     s["n_sub"] = n_sub
     s["mech"] = mech
+    # FP32 mode: cells releasing more than 1 K of heat per step (actively
+    # burning, where the reaction sub-steps are stiff) integrate them in FP64
+    s["theta_ign"] = THETA_IGN_BED
     return s
 
 
