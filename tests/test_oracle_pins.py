@@ -442,6 +442,7 @@ def test_P9_mass_fractions_sum_to_one_on_bed():
     """Species transport (with the correction flux) plus element-balanced
     chemistry keep sum_k Y_k = 1 in every cell, every step."""
     wl = W.cfg2_bed(nx=24, ny=12, nz=12, precision="fp64", bed=(4, 20), x_split=12, steps=0)
+    wl.setup["theta_ign"] = 1e-6  # count every reacting cell as active
     o = O.Oracle(wl.setup, wl.phi)
     o.init_state(wl.T0, wl.Y0)
     for _ in range(5):
