@@ -294,7 +294,7 @@ def _balanced_candidates(nreact: int):
     return cands
 
 
-def mech_synthetic9(seed=33, nr=21, T_ref=2000.0, conc_ref=None, n_sub_target=8,
+def mech_synthetic9(seed=33, nr=21, T_ref=1500.0, conc_ref=None, n_sub_target=8,
                     cp=1.0, R_over_M_in=0.2857):
     """Synthetic 9-species, 21-reversible-reaction mechanism.
 
@@ -306,13 +306,19 @@ def mech_synthetic9(seed=33, nr=21, T_ref=2000.0, conc_ref=None, n_sub_target=8,
     pseudo-first-order rate bound at T_ref and the reference concentrations
     gives h*kappa <= 0.5 with n_sub_target sub-steps.  Equilibrium constants
     are thermodynamically consistent: ln Kc = a + b/T with b = -dH/R from the
-    same formation-enthalpy table (dH is the molar reaction enthalpy), a ~ U[-2, 2]."""
+    same formation-enthalpy table (dH is the molar reaction enthalpy) and
+    a = sum_k s_kj sigma_k + dn_j ln(c0) from seeded species constants
+    sigma_k ~ U[-1, 1] and a standard-state concentration c0 = 1e-4."""
     rng = np.random.default_rng(seed)
     ns = 9
     comp = np.array(_SPECIES)
     M = (comp @ _ELEM_MASS).astype(float)
     cands = _balanced_candidates(8)
-    pick = rng.choice(len(cands), size=nr, replace=False)
+    # initiation from the fresh mixture (A2 + B2) is always present; the rest
+    # are drawn from the remaining candidates
+    init = [i for i, (lhs, _) in enumerate(cands) if sorted(lhs) == [0, 1]]
+    rest = [i for i in range(len(cands)) if i not in init]
+    pick = np.concatenate([init, rng.choice(rest, size=nr - len(init), replace=False)])
     nu_f = np.zeros((nr, ns), int)
     nu_r = np.zeros((nr, ns), int)
     for j, ci in enumerate(sorted(pick)):
@@ -325,37 +331,60 @@ def mech_synthetic9(seed=33, nr=21, T_ref=2000.0, conc_ref=None, n_sub_target=8,
             nu_r[j, s] += 1
     # formation enthalpy per unit mass (units cp*K): fuels and radicals positive,
     # products negative, diluent zero; "fuel-like -> product" is exothermic.
-    dhf = np.array([0.0, 0.0, -4000.0, 2000.0, 30000.0, 4000.0, 100.0, -1000.0, 0.0])
+    dhf = np.array([0.0, 0.0, -3000.0, 2000.0, 30000.0, 4000.0, 100.0, -1000.0, 0.0])
     dH = (nu_r - nu_f) @ (dhf * M)           # molar reaction enthalpy (cp*K*mass/mol)
     R_u = R_over_M_in * _mbar_in_synth9()    # gas constant in the same units
     lnKc_b = -dH / R_u
-    lnKc_a = rng.uniform(-2.0, 2.0, nr)
+    # entropy-like species constants: ln Kc_j = sum_k s_kj (sigma_k - h_k/(R T)),
+    # so the equilibrium constants are consistent around every reaction cycle
+    # plus dn_j ln(c0) for a standard-state concentration c0 typical of the
+    # lattice-unit concentrations (reactions changing the mole count)
+    sigma = rng.uniform(-1.0, 1.0, ns)
+    dn = (nu_r - nu_f).sum(axis=1)
+    lnKc_a = (nu_r - nu_f) @ sigma + dn * math.log(1e-4)
     theta = rng.uniform(0.0, 20000.0, nr)
     beta = rng.uniform(-1.0, 1.0, nr)
-    A = 10.0 ** rng.uniform(0.0, 3.0, nr)
-    if conc_ref is None:
-        conc_ref = np.full(ns, 0.05)
-    # pseudo-first-order bound for species k: sum over reactions consuming k of
-    # k(T_ref) * product of the other reactant concentrations
-    kf = A * T_ref ** beta * np.exp(-theta / T_ref)
-    kr = kf / np.exp(lnKc_a + lnKc_b / T_ref)
-    kap = np.zeros(ns)
-    for j in range(nr):
-        for nu, kk in ((nu_f[j], kf[j]), (nu_r[j], kr[j])):
-            for k in range(ns):
-                if nu[k] == 0:
-                    continue
-                other = kk
-                for m in range(ns):
-                    e = nu[m] - (1 if m == k else 0)
-                    other *= conc_ref[m] ** e
-                kap[k] += nu[k] * other
-    scale = (0.5 * n_sub_target) / float(kap.max())
-    A = A * scale
+    yref = np.maximum(np.maximum(SYNTH9_Y_IN, burnt_synth9()), 0.01)
+
+    def kappa(Avec, T):
+        """Pseudo-first-order consumption rate of each species at temperature T
+        (concentrations rho Y/M with rho ~ T_in/T, the larger of the inlet and
+        burnt fractions, at least 1 %), and the largest per-reaction term."""
+        conc = (T_IN / T) * yref / M if conc_ref is None else conc_ref
+        kf = Avec * T ** beta * np.exp(-theta / T)
+        kr = kf / np.exp(lnKc_a + lnKc_b / T)
+        kap = np.zeros(ns)
+        per = np.zeros(nr)
+        for j in range(nr):
+            for nu, kk in ((nu_f[j], kf[j]), (nu_r[j], kr[j])):
+                for k in range(ns):
+                    if nu[k] == 0:
+                        continue
+                    other = kk
+                    for m_ in range(ns):
+                        e = nu[m_] - (1 if m_ == k else 0)
+                        other *= conc[m_] ** e
+                    kap[k] += nu[k] * other
+                    per[j] = max(per[j], nu[k] * other)
+        return kap, per
+
+    # each reaction normalised by its largest rate over T_in..T_ref, then
+    # spread log-uniformly over three decades below a common target rate; the
+    # stiffness bound over the same range fixes n_sub (h kappa <= 0.5, at most
+    # 32 sub-steps, A scaled down if needed)
+    temps = np.linspace(T_IN, T_ref, 18)
+    per = np.max([kappa(np.ones(nr), T)[1] for T in temps], axis=0)
+    target = 0.5 * n_sub_target / 4.0
+    A = 10.0 ** rng.uniform(-3.0, 0.0, nr) * target / per
+    kmax = max(float(kappa(A, T)[0].max()) for T in temps)
+    if kmax > 0.5 * 32:
+        A *= 0.5 * 32 / kmax
+        kmax = 0.5 * 32
+    n_sub = int(min(32, max(1, math.ceil(kmax / 0.5))))
     return dict(M=M.tolist(), dhf=dhf.tolist(), mu_star=rng.uniform(0.7, 1.4, ns).tolist(),
                 nu_f=nu_f.tolist(), nu_r=nu_r.tolist(), A=A.tolist(), beta=beta.tolist(),
                 theta=theta.tolist(), rev=[1] * nr, lnKc_a=lnKc_a.tolist(),
-                lnKc_b=lnKc_b.tolist(), n_sub=int(n_sub_target))
+                lnKc_b=lnKc_b.tolist(), n_sub=n_sub)
 
 
 SYNTH9_Y_IN = [0.03, 0.30, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.67]
@@ -501,7 +530,8 @@ def cfg2_bed(nx=256, ny=128, nz=128, precision="fp32", seed=2, bed=(32, 224), x_
 
 
 def cfg3_bed(nx=384, ny=192, nz=192, precision="fp32", seed=3, bed=(48, 336), x_split=144,
-             porosity=0.45, steps=5000, sphere_share=0.0, mech_seed=33) -> Workload:
+             porosity=0.45, steps=5000, sphere_share=0.0, mech_seed=33,
+             T_burnt=1100.0) -> Workload:
     """3-D D3Q19 bed of seeded superquadrics, synthetic 9-species /
     21-reversible-reaction mechanism, Wilke mixture transport with constant
     Lewis numbers ~ U[0.8, 1.2], FP32 fields with FP64 reaction sub-steps."""
@@ -515,7 +545,7 @@ def cfg3_bed(nx=384, ny=192, nz=192, precision="fp32", seed=3, bed=(48, 336), x_
     shape = (nz, ny, nx)
     parts = superquadric_bed(shape, bed, 8.0, porosity, seed, sphere_share=sphere_share)
     phi = bed_phi(shape, parts, s["eta"], (False, True, True))
-    T0, Y0 = _split_init(shape, phi, x_split, T_IN, SYNTH9_Y_IN, 1500.0, burnt_synth9(),
+    T0, Y0 = _split_init(shape, phi, x_split, T_IN, SYNTH9_Y_IN, T_burnt, burnt_synth9(),
                          s["T_s"])
     wl = Workload(f"cfg3_superquadric_bed_d3q19_{nx}x{ny}x{nz}", s, phi, T0, Y0, None, steps)
     wl.particles = parts

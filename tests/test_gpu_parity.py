@@ -244,3 +244,43 @@ def test_full_size_bed_one_step_from_gpu_state():
             assert e <= 1e-5, (k, e)
         if k == "T" or k.startswith("Y"):
             assert e <= 1e-5, (k, e)
+
+
+def _crop9(precision):
+    wl = W.cfg3_bed(nx=37, ny=18, nz=14, precision=precision, bed=(6, 31), x_split=19, steps=0,
+                    T_burnt=1400.0)
+    wl.setup["theta_ign"] = 0.01
+    return wl
+
+
+def test_nine_species_crop_fp64():
+    """Synthetic 9-species / 21-reversible-reaction mechanism, Wilke mixture
+    transport, unequal Lewis numbers (correction flux), 3 explicit sub-steps."""
+    wl = _crop9("fp64")
+    say(f"{wl.name} fp64 300 steps")
+    ctx, orc = run_both(wl.setup, wl.phi, wl.T0, wl.Y0, 300)
+    errs = compare(ctx, orc)
+    say(errs)
+    assert max(errs.values()) <= 1e-12, errs
+    dg, do = ctx.diagnostics(), orc.diag()
+    assert dg["n_flagged_fp64"] == do[O.D_FLAGGED] > 0
+    assert abs(dg["enthalpy"] - do[O.D_ENTHALPY]) <= 1e-12 * abs(do[O.D_ENTHALPY])
+
+
+def test_nine_species_crop_fp32_1000_steps():
+    wl32, wl64 = _crop9("fp32"), _crop9("fp64")
+    say(f"{wl32.name} fp32 vs oracle, 1000 steps")
+    ctx = lb().Context(wl32.setup, wl32.phi)
+    ctx.init_state(wl32.T0, wl32.Y0)
+    ctx.step(1000)
+    orc = O.Oracle(wl64.setup, wl64.phi)
+    orc.init_state(wl64.T0, wl64.Y0)
+    orc.step(1000)
+    errs = compare(ctx, orc)
+    say(errs)
+    for k, e in errs.items():
+        if k.startswith("u"):
+            assert e <= 1e-5, (k, e)
+        if k == "T" or k.startswith("Y"):
+            assert e <= 1e-4, (k, e)
+    assert ctx.diagnostics()["n_flagged_fp64"] > 0
