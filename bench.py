@@ -58,9 +58,10 @@ def traffic_from_profiles(workload_name, bytes_alg):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, steps=1):
+def cpu_baseline(wl, target_s=15.0):
     """The FP64 CPU oracle, as it stands, on a bounded sample of the same
-    workload: `steps` step(s) of the full grid from the initial state."""
+    workload: whole-grid steps from the initial state, as many as fit in about
+    `target_s` seconds (at least two)."""
     from oracle import oracle as O
 
     wl64 = dict(wl.setup)
@@ -68,11 +69,15 @@ def cpu_baseline(wl, steps=1):
     orc = O.Oracle(wl64, wl.phi)
     orc.init_state(wl.T0, wl.Y0 if wl.setup["ns"] else None)
     t0 = time.perf_counter()
-    orc.step(steps)
+    orc.step(1)
+    first = time.perf_counter() - t0
+    more = max(1, int(target_s / max(first, 1e-3)) - 1)
+    orc.step(more)
     dt = time.perf_counter() - t0
-    return {"value": wl.cells * steps / dt / 1e6, "unit": "MLUPS", "cores": O.nthreads(),
-            "kind": "oracle",
-            "sample": f"{steps} step(s) of the full {wl.setup['nx']}x{wl.setup['ny']}x"
+    steps = 1 + more
+    return {"value": round(wl.cells * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": O.nthreads(), "kind": "oracle",
+            "sample": f"{steps} steps of the full {wl.setup['nx']}x{wl.setup['ny']}x"
                       f"{wl.setup['nz']} grid from the initial state, {dt:.1f} s"}
 
 
@@ -97,7 +102,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -167,7 +172,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

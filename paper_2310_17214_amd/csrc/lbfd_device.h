@@ -211,15 +211,40 @@ __device__ __forceinline__ void chem_apply(const Par<C>& P, C& T, C* Y, C rho, c
     T = T + hr * wT * P.inv_cp;
 }
 
-// n_sub explicit Euler sub-steps at constant pressure, in type C; the first
-// sub-step may reuse rates evaluated by the caller.
+// n_sub explicit Euler sub-steps at constant pressure, in type C.
 template <typename C, int NSM>
-__device__ __forceinline__ void chem_integrate(const Par<C>& P, C& T, C* Y, int first = 0) {
+__device__ __forceinline__ void chem_integrate(const Par<C>& P, C& T, C* Y) {
     C wk[LBFD_NA(NSM)], wT;
-    for (int n = first; n < P.n_sub; ++n) {
+    for (int n = 0; n < P.n_sub; ++n) {
         const C rho = eos<C, NSM>(P, T, Y);
         rates<C, NSM>(P, T, Y, rho, wk, wT);
         chem_apply<C, NSM>(P, T, Y, rho, wk, wT);
+    }
+}
+
+// The same n_sub sub-steps, carried as increments (dT, dY) on a fixed base
+// state (T0, Y0): the sub-step state is T0 + dT, and the caller gets the
+// increments at full precision (in FP32 the chemical heat release of a slow
+// cell is far below the rounding unit of T).  `wk`, `wT` and `rho0` hold the
+// rates already evaluated at the base state.
+template <typename C, int NSM>
+__device__ __forceinline__ void chem_increments(const Par<C>& P, C T0, const C* Y0, C rho0,
+                                                const C* wk0, C wT0, C& dT, C* dY) {
+    C hr = P.h_sub * rcp(rho0);
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) dY[k] = hr * wk0[k];
+    dT = hr * wT0 * P.inv_cp;
+    C wk[LBFD_NA(NSM)], wT, Y[LBFD_NA(NSM)];
+    for (int n = 1; n < P.n_sub; ++n) {
+        const C T = T0 + dT;
+#pragma unroll
+        for (int k = 0; k < NSM; ++k) Y[k] = Y0[k] + dY[k];
+        const C rho = eos<C, NSM>(P, T, Y);
+        rates<C, NSM>(P, T, Y, rho, wk, wT);
+        hr = P.h_sub * rcp(rho);
+#pragma unroll
+        for (int k = 0; k < NSM; ++k) dY[k] = dY[k] + hr * wk[k];
+        dT = dT + hr * wT * P.inv_cp;
     }
 }
 

@@ -105,7 +105,10 @@ def test_cfg1_cylinder_fp64_2000_steps():
 def _crop(precision, **kw):
     args = dict(nx=38, ny=17, nz=15, precision=precision, bed=(6, 30), x_split=18, steps=0)
     args.update(kw)
-    return W.cfg2_bed(**args)
+    wl = W.cfg2_bed(**args)
+    # low enough that the FP64 reaction island takes cells in this small crop
+    wl.setup["theta_ign"] = 0.01
+    return wl
 
 
 def test_bed_crop_fp64():
