@@ -197,6 +197,18 @@ lbfd_status lbfd_synchronize(lbfd_ctx* ctx);
 /* Algorithmic HBM bytes one cell moves in one lbfd_step on this grid. */
 lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* ctx, double* bytes);
 
+/* Per-kernel launch timing (measurement hook).  While enabled, every launch
+ * of the fused step kernel and of the FP64 reaction-island kernel is
+ * bracketed by a pair of HIP events recorded on the context's stream.
+ * lbfd_kernel_time waits for the stream, returns the number of timed launches
+ * of `kernel` (LBFD_KERNEL_*) since timing was enabled and their mean
+ * duration in milliseconds (0 when there were none), and keeps counting.
+ * Enabling restarts the count.  The events are created by the library on
+ * first use and released by lbfd_destroy. */
+enum { LBFD_KERNEL_STEP = 0, LBFD_KERNEL_ISLAND = 1 };
+lbfd_status lbfd_set_timing(lbfd_ctx* ctx, int32_t enable);
+lbfd_status lbfd_kernel_time(lbfd_ctx* ctx, int32_t kernel, int64_t* launches, double* mean_ms);
+
 lbfd_status lbfd_destroy(lbfd_ctx* ctx);
 const char* lbfd_last_error(const lbfd_ctx* ctx);
 

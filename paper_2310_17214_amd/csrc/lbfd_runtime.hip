@@ -122,6 +122,10 @@ struct lbfd_ctx {
     int cur = 0, odd = 0;
     int64_t steps = 0;
     std::string err;
+    // launch timing: event pairs per kernel kind, reused across enable cycles
+    bool timing = false;
+    std::vector<hipEvent_t> ev[2];
+    size_t ev_used[2] = {0, 0};
 };
 
 namespace {
@@ -305,6 +309,26 @@ lbfd_status validate_grid(const lbfd_grid* g, std::string& msg) {
     return LBFD_OK;
 }
 
+// Record the start (end = false) or end event of a timed launch of `kernel`.
+hipError_t time_mark(lbfd_ctx* c, int kernel, bool end) {
+    if (!c->timing) return hipSuccess;
+    std::vector<hipEvent_t>& v = c->ev[kernel];
+    size_t& used = c->ev_used[kernel];
+    const size_t slot = end ? used - 1 : used;
+    if (!end) {
+        if (2 * used + 2 > v.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t e;
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+                v.push_back(e);
+            }
+        }
+        ++used;
+    }
+    return hipEventRecord(v[2 * slot + (end ? 1 : 0)], c->stream);
+}
+
 template <typename R>
 lbfd_status launch_step(lbfd_ctx* c, int phase) {
     StepArgs<R> a;
@@ -329,12 +353,19 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.phase = phase;
     a.diag = 1;
     hipError_t e;
-    if constexpr (sizeof(R) == 4) {
+    if ((e = time_mark(c, LBFD_KERNEL_STEP, false)) != hipSuccess)
+        return hip_check(c, e, "timing event");
+    if constexpr (sizeof(R) == 4)
         e = launch_step_f32(c->dim, c->nsm, a, c->L.grid, c->stream);
-        if (e == hipSuccess && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM))
-            e = launch_island_f32(c->dim, c->nsm, a, c->L.grid, c->stream);
-    } else {
+    else
         e = launch_step_f64(c->dim, c->nsm, a, c->L.grid, c->stream);
+    if (e == hipSuccess) e = time_mark(c, LBFD_KERNEL_STEP, true);
+    if constexpr (sizeof(R) == 4) {
+        if (e == hipSuccess && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM)) {
+            e = time_mark(c, LBFD_KERNEL_ISLAND, false);
+            if (e == hipSuccess) e = launch_island_f32(c->dim, c->nsm, a, c->L.grid, c->stream);
+            if (e == hipSuccess) e = time_mark(c, LBFD_KERNEL_ISLAND, true);
+        }
     }
     return hip_check(c, e, "step kernel launch");
 }
@@ -714,7 +745,38 @@ lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* c, double* bytes) {
     return LBFD_OK;
 }
 
+lbfd_status lbfd_set_timing(lbfd_ctx* c, int32_t enable) {
+    if (!c) return LBFD_E_INVAL;
+    c->timing = enable != 0;
+    c->ev_used[0] = c->ev_used[1] = 0;
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_kernel_time(lbfd_ctx* c, int32_t kernel, int64_t* launches, double* mean_ms) {
+    if (!c || !launches || !mean_ms || kernel < 0 || kernel > 1) return LBFD_E_INVAL;
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "kernel time"))) return st;
+    double sum = 0.0;
+    const size_t n = c->ev_used[kernel];
+    for (size_t i = 0; i < n; ++i) {
+        float ms = 0.f;
+        st = hip_check(c, hipEventElapsedTime(&ms, c->ev[kernel][2 * i], c->ev[kernel][2 * i + 1]),
+                       "kernel time");
+        if (st) return st;
+        sum += ms;
+    }
+    *launches = (int64_t)n;
+    *mean_ms = n ? sum / (double)n : 0.0;
+    return LBFD_OK;
+}
+
 lbfd_status lbfd_destroy(lbfd_ctx* c) {
+    if (c) {
+        if (set_device(c) == LBFD_OK)
+            for (auto& v : c->ev)
+                for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    }
     delete c;
     return LBFD_OK;
 }

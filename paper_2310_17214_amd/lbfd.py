@@ -28,7 +28,9 @@ FD_BC = {"periodic": 0, "dirichlet": 1, "neumann": 2}
 EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd_set_mechanism",
             "lbfd_set_params", "lbfd_init_state", "lbfd_set_populations", "lbfd_step",
             "lbfd_step_phase", "lbfd_read", "lbfd_diagnostics", "lbfd_synchronize",
-            "lbfd_step_bytes_per_cell", "lbfd_destroy", "lbfd_last_error"]
+            "lbfd_step_bytes_per_cell", "lbfd_set_timing", "lbfd_kernel_time",
+            "lbfd_destroy", "lbfd_last_error"]
+LBFD_KERNEL_STEP, LBFD_KERNEL_ISLAND = 0, 1
 
 
 class Grid(C.Structure):
@@ -92,6 +94,8 @@ def lib():
         L.lbfd_diagnostics.argtypes = [vp, C.POINTER(Diag)]
         L.lbfd_synchronize.argtypes = [vp]
         L.lbfd_step_bytes_per_cell.argtypes = [vp, _dp]
+        L.lbfd_set_timing.argtypes = [vp, C.c_int32]
+        L.lbfd_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), _dp]
         L.lbfd_destroy.argtypes = [vp]
         L.lbfd_last_error.argtypes = [vp]
         L.lbfd_last_error.restype = C.c_char_p
@@ -266,3 +270,12 @@ class Context:
         b = C.c_double()
         self._check(lib().lbfd_step_bytes_per_cell(self._h, C.byref(b)))
         return b.value
+
+    def set_timing(self, enable=True):
+        self._check(lib().lbfd_set_timing(self._h, int(bool(enable))))
+
+    def kernel_time(self, kernel=LBFD_KERNEL_STEP):
+        """(timed launches, mean launch duration in ms) of one kernel kind."""
+        n, ms = C.c_int64(), C.c_double()
+        self._check(lib().lbfd_kernel_time(self._h, kernel, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
