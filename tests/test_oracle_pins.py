@@ -5,7 +5,9 @@ case that the paper's equations (or plain mathematics) fix, so that a
 plausible slip (dropped term, wrong sign or index, transposed operand) fails
 one of them.  Section and equation names refer to the paper.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -14,6 +16,14 @@ from oracle import oracle as O
 from paper_2310_17214_amd import workloads as W
 
 CS2 = 1.0 / 3.0
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
+_SA = GOLDEN["sutherland_air"]
+
+
+def suth(t):
+    """The paper's absolute Sutherland law (Eq. muT) with its air constants."""
+    ts, S = _SA["T_star_K"], _SA["S_K"]
+    return _SA["mu_star_Pa_s"] * (t / ts) ** 1.5 * (ts + S) / (t + S)
 
 
 def rel(a, b):
@@ -112,7 +122,6 @@ def test_P3_drag_decay_closed_form(dim):
     rho = s["rho_in"] * s["T_in"] / T
     x = T / s["T_in"]
     # viscosity from the paper's absolute Sutherland form (Eq. muT), scaled to the inlet value
-    suth = lambda t: (t / 273.0) ** 1.5 * (273.0 + 110.5) / (t + 110.5)
     mu = s["rho_in"] * s["nu_in"] * suth(T) / suth(s["T_in"])
     K = s["A_u"] * mu * (1 - phis) * phis ** 2 / s["eta"] ** 2
     r = (rho - K / 2) / (rho + K / 2)
@@ -171,7 +180,6 @@ def test_P7_interface_heat_exchange_recurrence():
     o = O.Oracle(s, np.full(shape, phis))
     T = 350.0
     o.init_state(np.full(shape, T))
-    suth = lambda t: (t / 273.0) ** 1.5 * (273.0 + 110.5) / (t + 110.5)
     for n in range(40):
         o.step(1)
         mu = s["rho_in"] * s["nu_in"] * suth(T) / suth(s["T_in"])
@@ -488,8 +496,25 @@ def test_P16_axis_permutation_symmetry():
 
 def test_a_t_fit_reproduces_paper_optimum():
     """The paper's fit of A_T* against T_wall/T_in (Sec. 4.2) returns the
-    separately quoted optimum A_T* = 70 at T_wall = 400 K within 1 %."""
-    assert abs(W.a_t_fit(400.0) - 70.0) / 70.0 < 0.01
+    separately quoted optimum A_T* = 70 at T_wall = 400 K within 1 %, and the
+    generator uses the printed fit coefficients."""
+    g, fit = GOLDEN["a_t_optimum_400K"], GOLDEN["a_t_fit"]
+    assert abs(W.a_t_fit(g["T_wall_K"]) - g["A_T_star"]) / g["A_T_star"] < 0.01
+    for r in (4.0 / 3.0, 1.5, 7.0 / 3.0, 3.0):
+        assert W.a_t_fit(300.0 * r) == pytest.approx(fit["intercept"] + fit["slope"] * r, rel=1e-15)
+    assert W.cfg1_cylinder().setup["A_u"] == GOLDEN["a_u_optimum"]["A_u_star"]
+
+
+def test_sutherland_ratio_matches_the_absolute_law():
+    """The closures use the Sutherland law as a ratio to the inlet state; it
+    must equal the paper's absolute law with its air constants (Eq. muT)
+    divided by its inlet value, whatever T* is."""
+    s = W.base_setup(2, 4, 4, 1, 0)
+    T = np.array([300.0, 450.0, 700.0, 1100.0, 1800.0])
+    for t in T:
+        mu, _, _ = O.mixture(s, t, [])
+        assert mu == pytest.approx(s["rho_in"] * s["nu_in"] * suth(t) / suth(s["T_in"]), rel=1e-14)
+    assert s["Pr"] == GOLDEN["prandtl"]["Pr"]
 
 
 # ----------------------------------------------------- open boundaries
