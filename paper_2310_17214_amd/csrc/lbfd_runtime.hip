@@ -29,7 +29,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
     size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, parf, pard, scratch, red, total;
-    int nbx, nby, zc, nblocks, grid;  // step kernel: 32 x 8 tiles marching zc planes,
+    int nbx, nby, zc, nblocks, grid;  // step kernel: 64 x TH tiles of one plane,
                                       // grid padded to a multiple of the 8 XCDs
     int nlin;                     // one-cell-per-thread kernels
 };
