@@ -1,0 +1,165 @@
+"""Pins of the CPU surrogate reference (no GPU).
+
+The surrogate reference is checked against facts outside itself: the
+bfloat16 rounding of a library, central differences of the loss, the sign
+property of the first Adam step, a hand-built ReLU network with a closed-form
+output, the projection invariant, the exact one-step Arrhenius source and the
+element balance of the synthetic mechanism.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from oracle import surrogate_ref as S
+from paper_2310_17214_amd import workloads as W
+
+
+def test_bf16_round_matches_library_conversion():
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.normal(size=4000) * 10.0 ** rng.integers(-30, 30, 4000),
+                        [0.0, -0.0, 1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 65504.0, 2.0 ** -130,
+                         3.3895313892515355e38]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(S.bf16_round(x), ref)
+    assert S.bf16_round(1 + 2 ** -8) == 1.0 and S.bf16_round(1 + 3 * 2 ** -8) == 1 + 2 ** -6
+
+
+def _small_problem(seed=3, n=24, ns=9):
+    rng = np.random.default_rng(seed)
+    w = S.init_weights(ns, seed)
+    w = {k: v.astype(np.float64) + (0.05 * rng.normal(size=v.shape) if k[0] == "b" else 0.0)
+         for k, v in w.items()}
+    x = rng.normal(size=(n, S.n_in(ns)))
+    t = rng.normal(size=(n, ns))
+    return w, x, t
+
+
+def test_backprop_matches_central_differences():
+    """dL/dw by backpropagation against FP64 central differences, <= 1e-6
+    relative, on entries of every weight and bias array."""
+    w, x, t = _small_problem()
+    _, g = S.loss_and_grad(w, x, t)
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        flat = w[k].reshape(-1)
+        gflat = g[k].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            wp = {kk: vv.copy() for kk, vv in w.items()}
+            wm = {kk: vv.copy() for kk, vv in w.items()}
+            wp[k].reshape(-1)[idx] += h
+            wm[k].reshape(-1)[idx] -= h
+            fd = (S.loss_and_grad(wp, x, t)[0] - S.loss_and_grad(wm, x, t)[0]) / (2 * h)
+            scale = max(abs(fd), 1e-3 * np.abs(gflat).max())
+            assert abs(gflat[idx] - fd) <= 1e-6 * scale + 1e-12, (k, idx, gflat[idx], fd)
+
+
+def test_first_adam_step_moves_each_weight_by_lr_sign_of_gradient():
+    """With zero moments, the bias-corrected first step is -lr g/(|g| + eps)."""
+    w, x, t = _small_problem()
+    _, g = S.loss_and_grad(w, x, t)
+    zero = {k: np.zeros_like(v) for k, v in w.items()}
+    nw, nm, nv = S.adam(w, g, zero, zero, 1, lr=1e-3)
+    for k in w:
+        big = np.abs(g[k]) > 1e-4
+        step = nw[k] - w[k]
+        assert np.allclose(step[big], -1e-3 * np.sign(g[k][big]), rtol=1e-3, atol=0)
+        assert np.allclose(nm[k], 0.1 * g[k]) and np.allclose(nv[k], 0.001 * g[k] ** 2)
+
+
+def test_hand_built_relu_network_computes_absolute_value():
+    """W1 takes +x0 and -x0, W2 copies them, W3 adds: the output is
+    |x0| + b3, exactly, with and without the bfloat16 rounding points (all
+    values chosen representable)."""
+    ns = 4
+    ni = S.n_in(ns)
+    w = {k: np.zeros_like(v) for k, v in S.init_weights(ns, 0).items()}
+    w["W1"][0, 0], w["W1"][1, 0] = 1.0, -1.0
+    w["W2"][0, 0], w["W2"][1, 1] = 1.0, 1.0
+    w["W3"][2, 0], w["W3"][2, 1] = 1.0, 1.0
+    w["b3"][2] = 0.25
+    x = np.zeros((5, ni))
+    x[:, 0] = [-3.0, -0.5, 0.0, 0.75, 2.0]
+    for emulate in (False, True):
+        y = S.forward(w, x, emulate)
+        assert np.array_equal(y[:, 2], np.abs(x[:, 0]) + 0.25)
+        assert np.array_equal(y[:, [0, 1, 3]], np.zeros((5, 3)))
+
+
+def _model(ns, seed=7):
+    w = S.init_weights(ns, seed)
+    X = S.features(np.linspace(400, 1500, 50), np.full((50, ns), 1.0 / ns))
+    Yt = np.random.default_rng(seed).normal(size=(50, ns)) * 1e-3
+    return w, S.fit_norm(X, Yt)
+
+
+def test_projection_keeps_mass_fractions_summing_to_one():
+    wl = W.cfg3_bed(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0)
+    s = wl.setup
+    w, norm = _model(9)
+    Y = np.full((6, 9), 1.0 / 9)
+    T = np.linspace(500, 1400, 6)
+    omega, omega_T, fb, raw = S.source(w, norm, s, T, Y)
+    assert np.abs(omega.sum(1)).max() <= 1e-15 * np.abs(raw).sum(1).max()
+    assert np.allclose(omega_T, -(omega * np.asarray(s["mech"]["dhf"])).sum(1), rtol=1e-15)
+
+
+def test_fallback_flags():
+    wl = W.cfg3_bed(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0)
+    s = wl.setup
+    w, norm = _model(9)
+    # a prediction fixed at a small balanced source: only the checks decide
+    w["W3"][:] = 0.0
+    w["b3"][:] = 0.0
+    norm = dict(norm, mu_y=np.array([1e-4, -1e-4] + [0.0] * 7))
+    Y = np.full((3, 9), 1.0 / 9)
+    T = np.array([800.0, 2000.0, 900.0])  # 2000 K is outside the envelope [400, 1500]
+    _, _, fb, _ = S.source(w, norm, s, T, Y)
+    assert list(fb) == [False, True, False]
+    # a prediction that would drive a mass fraction negative
+    norm2 = dict(norm, mu_y=norm["mu_y"] - 10.0, sd_y=norm["sd_y"])
+    assert S.source(w, norm2, s, T[:1], Y[:1])[2][0]
+    # a large residual: every raw source of the same sign
+    norm3 = dict(norm, mu_y=np.full(9, 1.0), sd_y=np.full(9, 1e-9))
+    assert S.source(w, norm3, s, T[:1], Y[:1])[2][0]
+
+
+def test_step_source_one_step_mechanism_is_the_arrhenius_rate():
+    """n_sub = 1: omega_bar_k = rho dY_k = M_k s_k Q with
+    Q = A exp(-theta/T) [F][O] (mass action, Eq. 8) and dt = 1."""
+    wl = W.cfg2_bed(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0)
+    s = wl.setup
+    m = s["mech"]
+    T = np.array([900.0, 1100.0, 1300.0])
+    Y = np.array([[0.3, 0.4, 0.2, 0.1], [0.1, 0.3, 0.5, 0.1], [0.05, 0.15, 0.7, 0.1]])
+    got = S.step_source(s, T, Y)
+    for i in range(3):
+        rho = s["rho_in"] * s["T_in"] / T[i]  # all M = 1
+        Q = m["A"][0] * math.exp(-m["theta"][0] / T[i]) * rho * Y[i, 0] * rho * Y[i, 1]
+        ref = np.array([-Q, -Q, 2 * Q, 0.0])
+        assert np.allclose(got[i], ref, rtol=1e-13, atol=1e-15 * abs(Q))
+
+
+def test_step_source_conserves_elements_of_the_synthetic_mechanism():
+    wl = W.cfg3_bed(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0, T_burnt=1400.0)
+    s = wl.setup
+    comp = np.array(W._SPECIES, float)
+    M = np.asarray(s["mech"]["M"], float)
+    rng = np.random.default_rng(2)
+    Y = rng.dirichlet(np.ones(9), size=8)
+    T = rng.uniform(900, 1800, 8)
+    om = S.step_source(s, T, Y)
+    elem = (om / M) @ comp
+    assert np.abs(elem).max() <= 1e-12 * np.abs(om / M).max()
+    assert np.abs(om.sum(1)).max() <= 1e-12 * np.abs(om).max()
+
+
+def test_fit_norm_floors_constant_inputs():
+    X = S.features(np.linspace(300, 900, 10), np.full((10, 4), 0.25))
+    nrm = S.fit_norm(X, np.ones((10, 4)))
+    assert nrm["sd_x"][1] == pytest.approx(1e-12)
+    assert np.all(((X - nrm["mu_x"]) / nrm["sd_x"])[:, 1] == 0.0)
+    assert np.allclose(nrm["sd_y"], 1e-12)
