@@ -197,15 +197,57 @@ lbfd_status lbfd_synchronize(lbfd_ctx* ctx);
 /* Algorithmic HBM bytes one cell moves in one lbfd_step on this grid. */
 lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* ctx, double* bytes);
 
+/* ------------------------------------------------------------------------
+ * Chemistry surrogate (FP32 mode).  A perceptron n_in -> 256 -> 256 -> n_out
+ * with ReLU (BF16 operands on the matrix cores, FP32 accumulation and
+ * biases) replaces the reaction sub-steps of every step (Eqs. 8 and 9): from
+ * the post-transport state x = (T*, p, Y*_1..Y*_ns), n_in = 2 + ns,
+ * n_out = ns, it predicts the step-integrated sources
+ * w_k = rho* (Y_k^chem - Y*_k)/dt, de-standardised as mu_y + sd_y * yhat.
+ * The prediction is projected to sum_k w_k = 0 (w_k -= Y*_k sum_m w_m) and
+ * applied as Y_k = Y*_k + w_k/rho*, T = T* + w_T/(rho* c_p),
+ * w_T = -sum_k dh_k w_k.  A cell takes the exact FP64 reaction step instead
+ * (counted in n_fallback and n_flagged_fp64) when an input lies outside the
+ * training envelope, when |sum w| > 0.05 (sum |w| + 1e-30) before the
+ * projection, or when the update would give some Y_k < -1e-8.
+ * ------------------------------------------------------------------------ */
+
+/* Install (or, with weights == NULL, remove) the surrogate.  Host arrays,
+ * copied during the call:
+ *   weights  FP32, row-major, concatenated: W1 [256][n_in], b1 [256],
+ *            W2 [256][256], b2 [256], W3 [n_out][256], b3 [n_out];
+ *   norm     mu_x [n_in], sd_x [n_in], mu_y [n_out], sd_y [n_out] (sd > 0);
+ *   envelope lo [n_in], hi [n_in] of the training inputs.
+ * The feature p is the constant 1.  LBFD_E_UNSUPPORTED in FP64 mode or
+ * outside 1 <= n_species <= 14; LBFD_E_INVAL on non-finite weights. */
+lbfd_status lbfd_set_surrogate(lbfd_ctx* ctx, const float* weights, const float* norm,
+                               const float* envelope);
+
+/* Evaluate the installed surrogate on n states (device arrays, enqueued on
+ * the context's stream): T [n], Y [n_species][n] in; raw (de-standardised
+ * prediction before projection) [n_species][n], omega (after projection)
+ * [n_species][n] and fallback [n] (0/1) out. */
+lbfd_status lbfd_surrogate_eval(lbfd_ctx* ctx, const float* T, const float* Y, int32_t n,
+                                float* raw, float* omega, int32_t* fallback);
+
+/* Training pairs from the current state (device arrays, enqueued): for each
+ * cell index cells[i] (linear, x fastest), x[i] = (T, 1, Y_1..Y_ns) as
+ * [n][2 + ns] and the exact step-integrated source of one step of n_sub FP64
+ * sub-steps, y[i] = rho (Y^chem - Y)/dt as [n][ns].  Indices outside the
+ * grid give rows of NaN.  FP32 mode with a mechanism only. */
+lbfd_status lbfd_sample_states(lbfd_ctx* ctx, const int32_t* cells, int32_t n, float* x,
+                               float* y);
+
 /* Per-kernel launch timing (measurement hook).  While enabled, every launch
- * of the fused step kernel and of the FP64 reaction-island kernel is
+ * of the fused step kernel, of the FP64 reaction-island kernel and of the
+ * surrogate kernel is
  * bracketed by a pair of HIP events recorded on the context's stream.
  * lbfd_kernel_time waits for the stream, returns the number of timed launches
  * of `kernel` (LBFD_KERNEL_*) since timing was enabled and their mean
  * duration in milliseconds (0 when there were none), and keeps counting.
  * Enabling restarts the count.  The events are created by the library on
  * first use and released by lbfd_destroy. */
-enum { LBFD_KERNEL_STEP = 0, LBFD_KERNEL_ISLAND = 1 };
+enum { LBFD_KERNEL_STEP = 0, LBFD_KERNEL_ISLAND = 1, LBFD_KERNEL_SURROGATE = 2 };
 lbfd_status lbfd_set_timing(lbfd_ctx* ctx, int32_t enable);
 lbfd_status lbfd_kernel_time(lbfd_ctx* ctx, int32_t kernel, int64_t* launches, double* mean_ms);
 

@@ -269,6 +269,7 @@ struct StepArgs {
     int odd;              // AA parity of this step
     int phase;            // PH_* mask
     int diag;             // write diagnostics partials
+    int sur;              // FP32 surrogate mode: reactions left to the surrogate kernels
 };
 
 template <typename R>

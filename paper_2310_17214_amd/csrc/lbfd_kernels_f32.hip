@@ -1,7 +1,9 @@
 // lbfd_kernels_f32.hip -- float instantiations of the fused step, read and
-// init kernels (D2Q9/D3Q19 x species bound 0/4/9/16).
+// init kernels (D2Q9/D3Q19 x species bound 0/4/9/16), the FP64 reaction
+// island and the chemistry surrogate kernels.
 #include "lbfd_device.h"
 #include "lbfd_kernels.inc"
+#include "lbfd_mlp.inc"
 #include "lbfd_launch.h"
 
 namespace lbfd {
@@ -44,6 +46,35 @@ hipError_t launch_island_f32(int dim, int nsm, const StepArgs<float>& a, int gri
     case 4: return launch_island_t<4>(dim, a, grid, s);
     case 9: return launch_island_t<9>(dim, a, grid, s);
     default: return launch_island_t<16>(dim, a, grid, s);
+    }
+}
+hipError_t launch_mlp_step_f32(int dim, int nsm, const StepArgs<float>& a, const SurWeights* gw,
+                               const SurPar* sp, int grid, hipStream_t s) {
+    switch (nsm) {
+    case 4: return launch_mlp_step_t<4>(dim, a, gw, sp, grid, s);
+    case 9: return launch_mlp_step_t<9>(dim, a, gw, sp, grid, s);
+    case 16: return launch_mlp_step_t<16>(dim, a, gw, sp, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+hipError_t launch_mlp_eval_f32(int nsm, const float* T, const float* Y, int n, float* raw, float* w,
+                               int* fb, const Par<float>* P, const SurWeights* gw,
+                               const SurPar* sp, int grid, hipStream_t s) {
+    switch (nsm) {
+    case 4: return launch_mlp_eval_t<4>(T, Y, n, raw, w, fb, P, gw, sp, grid, s);
+    case 9: return launch_mlp_eval_t<9>(T, Y, n, raw, w, fb, P, gw, sp, grid, s);
+    case 16: return launch_mlp_eval_t<16>(T, Y, n, raw, w, fb, P, gw, sp, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+hipError_t launch_sample_f32(int nsm, const float* T, const float* Y, int N, const int* cells,
+                             int n, float* x, float* y, const Par<double>* PD, float p_in,
+                             hipStream_t s) {
+    switch (nsm) {
+    case 4: return launch_sample_t<4>(T, Y, N, cells, n, x, y, PD, p_in, s);
+    case 9: return launch_sample_t<9>(T, Y, N, cells, n, x, y, PD, p_in, s);
+    case 16: return launch_sample_t<16>(T, Y, N, cells, n, x, y, PD, p_in, s);
+    default: return hipErrorInvalidValue;
     }
 }
 }  // namespace lbfd

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lbfd_device.h"
+#include "lbfd_mlp.h"
 
 namespace lbfd {
 hipError_t launch_step_f32(int dim, int nsm, const StepArgs<float>& a, int grid, hipStream_t s);
@@ -13,7 +14,16 @@ hipError_t launch_macro_f64(int dim, int nsm, const MacroArgs<double>& a, int gr
 hipError_t launch_init_f32(int dim, int nsm, const InitArgs<float>& a, int grid, hipStream_t s);
 hipError_t launch_init_f64(int dim, int nsm, const InitArgs<double>& a, int grid, hipStream_t s);
 hipError_t launch_island_f32(int dim, int nsm, const StepArgs<float>& a, int grid, hipStream_t s);
-// cell rows per workgroup tile of the step kernel (tiles are 32 cells wide)
+// chemistry surrogate (FP32 only; species buckets 4, 9, 16)
+hipError_t launch_mlp_step_f32(int dim, int nsm, const StepArgs<float>& a, const SurWeights* gw,
+                               const SurPar* sp, int grid, hipStream_t s);
+hipError_t launch_mlp_eval_f32(int nsm, const float* T, const float* Y, int n, float* raw, float* w,
+                               int* fb, const Par<float>* P, const SurWeights* gw,
+                               const SurPar* sp, int grid, hipStream_t s);
+hipError_t launch_sample_f32(int nsm, const float* T, const float* Y, int N, const int* cells,
+                             int n, float* x, float* y, const Par<double>* PD, float p_in,
+                             hipStream_t s);
+// cell rows per workgroup tile of the step kernel (tiles are 64 cells wide)
 int step_tile_h_f32(int dim, int nsm);
 int step_tile_h_f64(int dim, int nsm);
 }  // namespace lbfd

@@ -14,6 +14,7 @@
 #include "lbfd.h"
 #include "lbfd_device.h"
 #include "lbfd_launch.h"
+#include "lbfd_mlp.h"
 
 using namespace lbfd;
 
@@ -28,7 +29,7 @@ struct HostMech {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, parf, pard, scratch, red, total;
+    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, parf, pard, scratch, red, sw, sp, total;
     int nbx, nby, zc, nblocks, grid;  // step kernel: 64 x TH tiles of one plane,
                                       // grid padded to a multiple of the 8 XCDs
     int nlin;                     // one-cell-per-thread kernels
@@ -72,6 +73,8 @@ Layout make_layout(const lbfd_grid& gr) {
     L.pard = take(sizeof(Par<double>));
     L.scratch = take(5 * N * sizeof(double));
     L.red = take(64 * sizeof(double));
+    L.sw = take(sizeof(SurWeights));  // chemistry surrogate: packed weights
+    L.sp = take(sizeof(SurPar));
     L.total = off;
     return L;
 }
@@ -124,8 +127,11 @@ struct lbfd_ctx {
     std::string err;
     // launch timing: event pairs per kernel kind, reused across enable cycles
     bool timing = false;
-    std::vector<hipEvent_t> ev[2];
-    size_t ev_used[2] = {0, 0};
+    std::vector<hipEvent_t> ev[3];
+    size_t ev_used[3] = {0, 0, 0};
+    // chemistry surrogate
+    bool sur = false;
+    int n_cu = 0;
 };
 
 namespace {
@@ -352,6 +358,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.odd = c->odd;
     a.phase = phase;
     a.diag = 1;
+    a.sur = sizeof(R) == 4 && c->sur && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM);
     hipError_t e;
     if ((e = time_mark(c, LBFD_KERNEL_STEP, false)) != hipSuccess)
         return hip_check(c, e, "timing event");
@@ -361,6 +368,14 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
         e = launch_step_f64(c->dim, c->nsm, a, c->L.grid, c->stream);
     if (e == hipSuccess) e = time_mark(c, LBFD_KERNEL_STEP, true);
     if constexpr (sizeof(R) == 4) {
+        if (e == hipSuccess && a.sur) {
+            e = time_mark(c, LBFD_KERNEL_SURROGATE, false);
+            if (e == hipSuccess)
+                e = launch_mlp_step_f32(c->dim, c->nsm, a, dptr<SurWeights>(c, c->L.sw),
+                                        dptr<SurPar>(c, c->L.sp),
+                                        std::min(c->n_cu, c->L.nblocks), c->stream);
+            if (e == hipSuccess) e = time_mark(c, LBFD_KERNEL_SURROGATE, true);
+        }
         if (e == hipSuccess && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM)) {
             e = time_mark(c, LBFD_KERNEL_ISLAND, false);
             if (e == hipSuccess) e = launch_island_f32(c->dim, c->nsm, a, c->L.grid, c->stream);
@@ -452,7 +467,9 @@ lbfd_status lbfd_create(const lbfd_grid* grid, void* dev_workspace, size_t bytes
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->ws = reinterpret_cast<char*>(dev_workspace);
     std::memset(&c->params, 0, sizeof(c->params));
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess || c->n_cu <= 0) {
         delete c;
         return LBFD_E_DEVICE;
     }
@@ -745,15 +762,145 @@ lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* c, double* bytes) {
     return LBFD_OK;
 }
 
+// ---------------------------------------------------------- surrogate
+namespace {
+uint16_t bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__bf16 to_bf16(float f) {
+    const uint16_t b = bf16_rne(f);
+    __bf16 r;
+    std::memcpy(&r, &b, 2);
+    return r;
+}
+}  // namespace
+
+lbfd_status lbfd_set_surrogate(lbfd_ctx* c, const float* w, const float* norm, const float* env) {
+    if (!c) return LBFD_E_INVAL;
+    if (!w) {
+        c->sur = false;
+        return LBFD_OK;
+    }
+    if (!norm || !env) return LBFD_E_INVAL;
+    if (!c->fp32) return fail(c, LBFD_E_UNSUPPORTED, "the surrogate runs in FP32 mode only");
+    const int ns = c->ns, ni = 2 + ns, no = ns, H = MLP_H;
+    if (ns < 1 || ni > MLP_KIN || no > MLP_OUT)
+        return fail(c, LBFD_E_UNSUPPORTED, "surrogate needs 1..14 species");
+    const float* W1 = w;
+    const float* b1 = W1 + H * ni;
+    const float* W2 = b1 + H;
+    const float* b2 = W2 + H * H;
+    const float* W3 = b2 + H;
+    const float* b3 = W3 + no * H;
+    const size_t nw = (size_t)(b3 + no - w);
+    for (size_t i = 0; i < nw; ++i)
+        if (!std::isfinite(w[i])) return fail(c, LBFD_E_INVAL, "non-finite surrogate weight");
+    std::vector<SurWeights> hw(1);
+    SurWeights& S = hw[0];
+    std::memset(&S, 0, sizeof(S));
+    for (int m = 0; m < MLP_HT; ++m)
+        for (int l = 0; l < 64; ++l)
+            for (int j = 0; j < 8; ++j) {
+                const int k = mlp_k1(l, j);
+                S.w1[m][l][j] = to_bf16(k < ni ? W1[(32 * m + l % 32) * ni + k] : 0.f);
+            }
+    for (int m = 0; m < MLP_HT; ++m)
+        for (int q = 0; q < MLP_HC; ++q)
+            for (int l = 0; l < 64; ++l)
+                for (int j = 0; j < 8; ++j)
+                    S.w2[m][q][l][j] =
+                        to_bf16(W2[(32 * m + l % 32) * H + mlp_kh(q / 2, q % 2, l, j)]);
+    for (int q = 0; q < MLP_HC; ++q)
+        for (int l = 0; l < 64; ++l)
+            for (int j = 0; j < 8; ++j) {
+                const int o = l % 32;
+                S.w3[q][l][j] = to_bf16(o < no ? W3[o * H + mlp_kh(q / 2, q % 2, l, j)] : 0.f);
+            }
+    for (int i = 0; i < H; ++i) {
+        S.b1[i] = b1[i];
+        S.b2[i] = b2[i];
+    }
+    for (int o = 0; o < no; ++o) S.b3[o] = b3[o];
+    SurPar P;
+    std::memset(&P, 0, sizeof(P));
+    P.n_in = ni;
+    P.n_out = no;
+    P.enabled = 1;
+    for (int i = 0; i < ni; ++i) {
+        const float sd = norm[ni + i];
+        if (!(sd > 0.f) || !std::isfinite(norm[i]))
+            return fail(c, LBFD_E_INVAL, "input standard deviation must be positive");
+        P.mu_x[i] = norm[i];
+        P.inv_sd_x[i] = 1.f / sd;
+        P.lo[i] = env[i];
+        P.hi[i] = env[ni + i];
+    }
+    for (int o = 0; o < no; ++o) {
+        P.mu_y[o] = norm[2 * ni + o];
+        P.sd_y[o] = norm[2 * ni + no + o];
+    }
+    P.p_in = 1.f;
+    P.resid_tol = 0.05f;
+    P.pos_tol = -1e-8f;
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    if ((st = hip_check(c, hipMemcpyAsync(c->ws + c->L.sw, &S, sizeof(S), hipMemcpyHostToDevice,
+                                          c->stream), "surrogate upload")))
+        return st;
+    if ((st = hip_check(c, hipMemcpyAsync(c->ws + c->L.sp, &P, sizeof(P), hipMemcpyHostToDevice,
+                                          c->stream), "surrogate upload")))
+        return st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "surrogate upload"))) return st;
+    c->sur = true;
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_surrogate_eval(lbfd_ctx* c, const float* T, const float* Y, int32_t n,
+                                float* raw, float* omega, int32_t* fallback) {
+    if (!c || n < 0 || (n > 0 && (!T || !Y || !raw || !omega || !fallback))) return LBFD_E_INVAL;
+    if (!c->sur) return fail(c, LBFD_E_STATE, "no surrogate set");
+    if (!c->have_params || (c->ns > 0 && !c->have_mech))
+        return fail(c, LBFD_E_STATE, "params and mechanism first");
+    if (n == 0) return LBFD_OK;
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    const int waves = (n + 63) / 64;
+    const int grid = std::max(1, std::min(c->n_cu, (waves + 3) / 4));
+    return hip_check(c, launch_mlp_eval_f32(c->nsm, T, Y, n, raw, omega, fallback,
+                                            dptr<Par<float>>(c, c->L.parf),
+                                            dptr<SurWeights>(c, c->L.sw), dptr<SurPar>(c, c->L.sp),
+                                            grid, c->stream),
+                     "surrogate eval launch");
+}
+
+lbfd_status lbfd_sample_states(lbfd_ctx* c, const int32_t* cells, int32_t n, float* x, float* y) {
+    if (!c || n < 0 || (n > 0 && (!cells || !x || !y))) return LBFD_E_INVAL;
+    if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
+    if (!c->fp32 || c->ns < 1 || 2 + c->ns > MLP_KIN || c->mech.nr < 1)
+        return fail(c, LBFD_E_UNSUPPORTED, "sampling needs FP32 mode and a mechanism");
+    if (n == 0) return LBFD_OK;
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    const float* T = dptr<float>(c, c->cur ? c->L.T1 : c->L.T0);
+    const float* Y = dptr<float>(c, c->cur ? c->L.Y1 : c->L.Y0);
+    return hip_check(c, launch_sample_f32(c->nsm, T, Y, (int)c->N, cells, n, x, y,
+                                          dptr<Par<double>>(c, c->L.pard), 1.f, c->stream),
+                     "sample launch");
+}
+
 lbfd_status lbfd_set_timing(lbfd_ctx* c, int32_t enable) {
     if (!c) return LBFD_E_INVAL;
     c->timing = enable != 0;
-    c->ev_used[0] = c->ev_used[1] = 0;
+    c->ev_used[0] = c->ev_used[1] = c->ev_used[2] = 0;
     return LBFD_OK;
 }
 
 lbfd_status lbfd_kernel_time(lbfd_ctx* c, int32_t kernel, int64_t* launches, double* mean_ms) {
-    if (!c || !launches || !mean_ms || kernel < 0 || kernel > 1) return LBFD_E_INVAL;
+    if (!c || !launches || !mean_ms || kernel < 0 || kernel > 2) return LBFD_E_INVAL;
     lbfd_status st = set_device(c);
     if (st) return st;
     if ((st = hip_check(c, hipStreamSynchronize(c->stream), "kernel time"))) return st;

@@ -29,8 +29,9 @@ EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd
             "lbfd_set_params", "lbfd_init_state", "lbfd_set_populations", "lbfd_step",
             "lbfd_step_phase", "lbfd_read", "lbfd_diagnostics", "lbfd_synchronize",
             "lbfd_step_bytes_per_cell", "lbfd_set_timing", "lbfd_kernel_time",
+            "lbfd_set_surrogate", "lbfd_surrogate_eval", "lbfd_sample_states",
             "lbfd_destroy", "lbfd_last_error"]
-LBFD_KERNEL_STEP, LBFD_KERNEL_ISLAND = 0, 1
+LBFD_KERNEL_STEP, LBFD_KERNEL_ISLAND, LBFD_KERNEL_SURROGATE = 0, 1, 2
 
 
 class Grid(C.Structure):
@@ -94,6 +95,10 @@ def lib():
         L.lbfd_diagnostics.argtypes = [vp, C.POINTER(Diag)]
         L.lbfd_synchronize.argtypes = [vp]
         L.lbfd_step_bytes_per_cell.argtypes = [vp, _dp]
+        _fp = C.POINTER(C.c_float)
+        L.lbfd_set_surrogate.argtypes = [vp, _fp, _fp, _fp]
+        L.lbfd_surrogate_eval.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp]
+        L.lbfd_sample_states.argtypes = [vp, vp, C.c_int32, vp, vp]
         L.lbfd_set_timing.argtypes = [vp, C.c_int32]
         L.lbfd_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), _dp]
         L.lbfd_destroy.argtypes = [vp]
@@ -270,6 +275,48 @@ class Context:
         b = C.c_double()
         self._check(lib().lbfd_step_bytes_per_cell(self._h, C.byref(b)))
         return b.value
+
+    # ------------------------------------------------------ surrogate
+    def set_surrogate(self, weights, norm, envelope):
+        """Install the chemistry surrogate (flat FP32 arrays in the ABI's
+        layout), or remove it with weights=None."""
+        if weights is None:
+            self._check(lib().lbfd_set_surrogate(self._h, None, None, None))
+            return
+        fp = C.POINTER(C.c_float)
+        arrs = [np.ascontiguousarray(np.asarray(a, np.float32)) for a in (weights, norm, envelope)]
+        self._check(lib().lbfd_set_surrogate(self._h, *(a.ctypes.data_as(fp) for a in arrs)))
+
+    def surrogate_eval(self, T, Y):
+        """Surrogate on n states (torch float32 CUDA tensors T [n], Y [ns, n]):
+        returns (raw [ns, n], omega [ns, n], fallback [n]) as CUDA tensors."""
+        import torch
+
+        T = T.contiguous().float()
+        Y = Y.contiguous().float()
+        n = T.numel()
+        if Y.shape != (self.ns, n):
+            raise ValueError("Y must be [ns, n]")
+        raw = torch.empty((self.ns, n), dtype=torch.float32, device=T.device)
+        om = torch.empty_like(raw)
+        fb = torch.empty(n, dtype=torch.int32, device=T.device)
+        self._check(lib().lbfd_surrogate_eval(self._h, T.data_ptr(), Y.data_ptr(), n,
+                                              raw.data_ptr(), om.data_ptr(), fb.data_ptr()))
+        self.synchronize()
+        return raw, om, fb
+
+    def sample_states(self, cells):
+        """Training pairs at the given cells (int32 CUDA tensor of linear
+        indices): x [n, 2 + ns] and the exact step source y [n, ns]."""
+        import torch
+
+        cells = cells.contiguous().to(torch.int32)
+        n = cells.numel()
+        x = torch.empty((n, 2 + self.ns), dtype=torch.float32, device=cells.device)
+        y = torch.empty((n, self.ns), dtype=torch.float32, device=cells.device)
+        self._check(lib().lbfd_sample_states(self._h, cells.data_ptr(), n, x.data_ptr(),
+                                             y.data_ptr()))
+        return x, y
 
     def set_timing(self, enable=True):
         self._check(lib().lbfd_set_timing(self._h, int(bool(enable))))
