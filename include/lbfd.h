@@ -238,10 +238,54 @@ lbfd_status lbfd_surrogate_eval(lbfd_ctx* ctx, const float* T, const float* Y, i
 lbfd_status lbfd_sample_states(lbfd_ctx* ctx, const int32_t* cells, int32_t n, float* x,
                                float* y);
 
+/* ------------------------------------------------------------------------
+ * Surrogate training (offline, once per mechanism).  Mini-batch Adam
+ * (Kingma and Ba) on the mean-square error of the standardised outputs,
+ * L = mean over batch and outputs of (yhat - (y - mu_y)/sd_y)^2, with FP32
+ * master weights and moments and bf16 matrix-core products (FP32
+ * accumulation).  Deterministic: fixed-order reductions throughout.
+ * The trainer owns no memory: the caller passes a device workspace of
+ * lbfd_trainer_workspace_bytes(cfg) bytes, 256-byte aligned, and a stream;
+ * data arrays (x [n][2 + ns], y [n][ns] as written by lbfd_sample_states,
+ * batch indices [batch]) are device arrays that must stay valid while the
+ * enqueued work runs.
+ * ------------------------------------------------------------------------ */
+typedef struct lbfd_trainer lbfd_trainer;
+typedef struct {
+    int32_t n_species;   /* 1..14: n_in = 2 + ns inputs, ns outputs */
+    int32_t batch;       /* samples per step, a multiple of 256 */
+    float beta1, beta2, eps;  /* Adam constants (e.g. 0.9, 0.999, 1e-8) */
+} lbfd_train_cfg;
+
+lbfd_status lbfd_trainer_workspace_bytes(const lbfd_train_cfg* cfg, size_t* bytes);
+lbfd_status lbfd_trainer_create(const lbfd_train_cfg* cfg, void* dev_workspace, size_t bytes,
+                                void* hip_stream, lbfd_trainer** out);
+/* Standardisation statistics (FP64 mean and population standard deviation,
+ * floored at 1e-12 max(|mu|, 1)) and the input envelope [min, max] of n
+ * samples (enqueued). */
+lbfd_status lbfd_trainer_fit_norm(lbfd_trainer* tr, const float* x, const float* y, int32_t n);
+/* Master weights from the host (layout of lbfd_set_surrogate); resets the
+ * Adam moments and step count (waits for the stream). */
+lbfd_status lbfd_trainer_set_weights(lbfd_trainer* tr, const float* weights);
+/* One Adam step with learning rate lr on the batch rows idx[0..batch) of the
+ * n samples (indices outside [0, n) read as zero rows).  If loss is not NULL
+ * it waits and returns the batch's loss before the update. */
+lbfd_status lbfd_trainer_step(lbfd_trainer* tr, const float* x, const float* y, int32_t n,
+                              const int32_t* idx, float lr, double* loss);
+/* Gradient of the batch loss (host, weights layout) and the loss, without an
+ * update (waits). */
+lbfd_status lbfd_trainer_gradient(lbfd_trainer* tr, const float* x, const float* y, int32_t n,
+                                  const int32_t* idx, float* grad, double* loss);
+/* Weights, norm and envelope to the host in lbfd_set_surrogate's layouts
+ * (any may be NULL; waits). */
+lbfd_status lbfd_trainer_export(lbfd_trainer* tr, float* weights, float* norm, float* envelope);
+lbfd_status lbfd_trainer_destroy(lbfd_trainer* tr);
+const char* lbfd_trainer_last_error(const lbfd_trainer* tr);
+
 /* Per-kernel launch timing (measurement hook).  While enabled, every launch
  * of the fused step kernel, of the FP64 reaction-island kernel and of the
- * surrogate kernel is
- * bracketed by a pair of HIP events recorded on the context's stream.
+ * surrogate kernel is bracketed by a pair of HIP events recorded on the
+ * context's stream.
  * lbfd_kernel_time waits for the stream, returns the number of timed launches
  * of `kernel` (LBFD_KERNEL_*) since timing was enabled and their mean
  * duration in milliseconds (0 when there were none), and keeps counting.

@@ -25,6 +25,7 @@ UNITS = [
     ("lbfd_kernels_f32.hip", []),
     ("lbfd_kernels_f64.hip", ["-ffp-contract=off"]),
     ("lbfd_runtime.hip", []),
+    ("lbfd_train.hip", []),
 ]
 
 

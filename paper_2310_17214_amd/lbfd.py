@@ -30,8 +30,16 @@ EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd
             "lbfd_step_phase", "lbfd_read", "lbfd_diagnostics", "lbfd_synchronize",
             "lbfd_step_bytes_per_cell", "lbfd_set_timing", "lbfd_kernel_time",
             "lbfd_set_surrogate", "lbfd_surrogate_eval", "lbfd_sample_states",
+            "lbfd_trainer_workspace_bytes", "lbfd_trainer_create", "lbfd_trainer_fit_norm",
+            "lbfd_trainer_set_weights", "lbfd_trainer_step", "lbfd_trainer_gradient",
+            "lbfd_trainer_export", "lbfd_trainer_destroy", "lbfd_trainer_last_error",
             "lbfd_destroy", "lbfd_last_error"]
 LBFD_KERNEL_STEP, LBFD_KERNEL_ISLAND, LBFD_KERNEL_SURROGATE = 0, 1, 2
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("batch", C.c_int32), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float)]
 
 
 class Grid(C.Structure):
@@ -99,6 +107,16 @@ def lib():
         L.lbfd_set_surrogate.argtypes = [vp, _fp, _fp, _fp]
         L.lbfd_surrogate_eval.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp]
         L.lbfd_sample_states.argtypes = [vp, vp, C.c_int32, vp, vp]
+        L.lbfd_trainer_workspace_bytes.argtypes = [C.POINTER(TrainCfg), C.POINTER(C.c_size_t)]
+        L.lbfd_trainer_create.argtypes = [C.POINTER(TrainCfg), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lbfd_trainer_fit_norm.argtypes = [vp, vp, vp, C.c_int32]
+        L.lbfd_trainer_set_weights.argtypes = [vp, _fp]
+        L.lbfd_trainer_step.argtypes = [vp, vp, vp, C.c_int32, vp, C.c_float, _dp]
+        L.lbfd_trainer_gradient.argtypes = [vp, vp, vp, C.c_int32, vp, _fp, _dp]
+        L.lbfd_trainer_export.argtypes = [vp, _fp, _fp, _fp]
+        L.lbfd_trainer_destroy.argtypes = [vp]
+        L.lbfd_trainer_last_error.argtypes = [vp]
+        L.lbfd_trainer_last_error.restype = C.c_char_p
         L.lbfd_set_timing.argtypes = [vp, C.c_int32]
         L.lbfd_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), _dp]
         L.lbfd_destroy.argtypes = [vp]
@@ -326,3 +344,116 @@ class Context:
         n, ms = C.c_int64(), C.c_double()
         self._check(lib().lbfd_kernel_time(self._h, kernel, C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+
+HIDDEN = 256
+
+
+def surrogate_param_count(ns):
+    ni = 2 + ns
+    return HIDDEN * ni + HIDDEN + HIDDEN * HIDDEN + HIDDEN + ns * HIDDEN + ns
+
+
+class Trainer:
+    """Surrogate trainer on one GPU (owns a torch workspace and a C trainer).
+    Data arrays are torch float32 CUDA tensors x [n, 2 + ns], y [n, ns]."""
+
+    def __init__(self, n_species, batch=4096, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible")
+        L = lib()
+        self.ns, self.batch = n_species, batch
+        self.np = surrogate_param_count(n_species)
+        self._cfg = TrainCfg(n_species, batch, beta1, beta2, eps)
+        nbytes = C.c_size_t()
+        st = L.lbfd_trainer_workspace_bytes(C.byref(self._cfg), C.byref(nbytes))
+        if st != LBFD_OK:
+            raise LbfdError(st, "trainer configuration")
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = L.lbfd_trainer_create(C.byref(self._cfg), C.c_void_p(base + (-base) % 256),
+                                   nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != LBFD_OK:
+            raise LbfdError(st, "trainer create")
+        self._h = h
+
+    def _check(self, st):
+        if st != LBFD_OK:
+            raise LbfdError(st, lib().lbfd_trainer_last_error(self._h).decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().lbfd_trainer_destroy(h)
+            self._h = None
+
+    def fit_norm(self, x, y):
+        self._data = (x.contiguous(), y.contiguous())
+        self._check(lib().lbfd_trainer_fit_norm(self._h, self._data[0].data_ptr(),
+                                                self._data[1].data_ptr(), x.shape[0]))
+
+    def set_weights(self, w):
+        a = np.ascontiguousarray(np.asarray(w, np.float32))
+        if a.size != self.np:
+            raise ValueError(f"expected {self.np} weights")
+        self._check(lib().lbfd_trainer_set_weights(self._h, a.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def step(self, x, y, idx, lr, want_loss=False):
+        loss = C.c_double()
+        self._check(lib().lbfd_trainer_step(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                            idx.data_ptr(), float(lr),
+                                            C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def gradient(self, x, y, idx):
+        g = np.empty(self.np, np.float32)
+        loss = C.c_double()
+        self._check(lib().lbfd_trainer_gradient(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                                idx.data_ptr(), g.ctypes.data_as(C.POINTER(C.c_float)),
+                                                C.byref(loss)))
+        return g, loss.value
+
+    def export(self):
+        ni = 2 + self.ns
+        w = np.empty(self.np, np.float32)
+        nrm = np.empty(2 * ni + 2 * self.ns, np.float32)
+        env = np.empty(2 * ni, np.float32)
+        fp = C.POINTER(C.c_float)
+        self._check(lib().lbfd_trainer_export(self._h, w.ctypes.data_as(fp), nrm.ctypes.data_as(fp),
+                                              env.ctypes.data_as(fp)))
+        return w, nrm, env
+
+    def fit(self, x, y, epochs, lr, seed, lr_final=None, log=None):
+        """Epochs of shuffled mini-batches; the permutations come from a seeded
+        host generator and are passed to the device as batch indices.  The
+        learning rate decays geometrically from lr to lr_final.  Returns the
+        mean batch loss of each epoch."""
+        import torch
+
+        n = x.shape[0]
+        rng = np.random.default_rng(seed)
+        nb = n // self.batch
+        total = max(1, epochs * nb)
+        lr_final = lr if lr_final is None else lr_final
+        out = []
+        k = 0
+        for e in range(epochs):
+            perm = torch.tensor(rng.permutation(n)[: nb * self.batch].astype(np.int32),
+                                device=x.device)
+            losses = []
+            for b in range(nb):
+                rate = lr * (lr_final / lr) ** (k / total)
+                last = b == nb - 1
+                l = self.step(x, y, perm[b * self.batch:(b + 1) * self.batch], rate,
+                              want_loss=(b % 16 == 0) or last)
+                if l is not None:
+                    losses.append(l)
+                k += 1
+            out.append(float(np.mean(losses)))
+            if log:
+                log(f"epoch {e}: loss {out[-1]:.4e}")
+        return out
