@@ -206,10 +206,15 @@ lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* ctx, double* bytes);
  * w_k = rho* (Y_k^chem - Y*_k)/dt, de-standardised as mu_y + sd_y * yhat.
  * The prediction is projected to sum_k w_k = 0 (w_k -= Y*_k sum_m w_m) and
  * applied as Y_k = Y*_k + w_k/rho*, T = T* + w_T/(rho* c_p),
- * w_T = -sum_k dh_k w_k.  A cell takes the exact FP64 reaction step instead
- * (counted in n_fallback and n_flagged_fp64) when an input lies outside the
- * training envelope, when |sum w| > 0.05 (sum |w| + 1e-30) before the
- * projection, or when the update would give some Y_k < -1e-8.
+ * w_T = -sum_k dh_k w_k.  Before the projection a source that would take
+ * more of a species than the cell holds (w_k < -rho* Y*_k) is clipped to
+ * -rho* Y*_k.  A cell takes the exact FP64 reaction step instead (counted in
+ * n_fallback and n_flagged_fp64) when an input lies outside the training
+ * envelope widened on each side by 1 % of its range plus 0.05 sd_x, when
+ * such a clip
+ * exceeds 0.05 sd_y[k], when
+ * |sum w| > 0.05 (sum |w| + sum_k sd_y[k]) before the projection, or when
+ * the update would give some Y_k < -1e-8.
  * ------------------------------------------------------------------------ */
 
 /* Install (or, with weights == NULL, remove) the surrogate.  Host arrays,
@@ -217,7 +222,7 @@ lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* ctx, double* bytes);
  *   weights  FP32, row-major, concatenated: W1 [256][n_in], b1 [256],
  *            W2 [256][256], b2 [256], W3 [n_out][256], b3 [n_out];
  *   norm     mu_x [n_in], sd_x [n_in], mu_y [n_out], sd_y [n_out] (sd > 0);
- *   envelope lo [n_in], hi [n_in] of the training inputs.
+ *   envelope lo [n_in], hi [n_in] of the training inputs (hi >= lo).
  * The feature p is the constant 1.  LBFD_E_UNSUPPORTED in FP64 mode or
  * outside 1 <= n_species <= 14; LBFD_E_INVAL on non-finite weights. */
 lbfd_status lbfd_set_surrogate(lbfd_ctx* ctx, const float* weights, const float* norm,
@@ -225,8 +230,10 @@ lbfd_status lbfd_set_surrogate(lbfd_ctx* ctx, const float* weights, const float*
 
 /* Evaluate the installed surrogate on n states (device arrays, enqueued on
  * the context's stream): T [n], Y [n_species][n] in; raw (de-standardised
- * prediction before projection) [n_species][n], omega (after projection)
- * [n_species][n] and fallback [n] (0/1) out. */
+ * prediction after the overdraw clip, before projection) [n_species][n],
+ * omega (after projection) [n_species][n] and fallback [n] out: 0 when the
+ * update stands, else the failed checks, 1 envelope | 2 overdraw |
+ * 4 residual | 8 positivity. */
 lbfd_status lbfd_surrogate_eval(lbfd_ctx* ctx, const float* T, const float* Y, int32_t n,
                                 float* raw, float* omega, int32_t* fallback);
 
@@ -261,8 +268,8 @@ lbfd_status lbfd_trainer_workspace_bytes(const lbfd_train_cfg* cfg, size_t* byte
 lbfd_status lbfd_trainer_create(const lbfd_train_cfg* cfg, void* dev_workspace, size_t bytes,
                                 void* hip_stream, lbfd_trainer** out);
 /* Standardisation statistics (FP64 mean and population standard deviation,
- * floored at 1e-12 max(|mu|, 1)) and the input envelope [min, max] of n
- * samples (enqueued). */
+ * floored at 1e-12 max(|mu|, 1) and, for the mass-fraction inputs, at 1e-4)
+ * and the input envelope [min, max] of n samples (enqueued). */
 lbfd_status lbfd_trainer_fit_norm(lbfd_trainer* tr, const float* x, const float* y, int32_t n);
 /* Master weights from the host (layout of lbfd_set_surrogate); resets the
  * Adam moments and step count (waits for the stream). */

@@ -11,7 +11,7 @@ where Y^chem is the exact n_sub-sub-step explicit Euler integration of the
 Arrhenius sources from (T, Y) (the oracle's reactor), and the map
     x = (T, p, Y_1..Y_ns)  ->  omega_bar_1..omega_bar_ns
 is a 2-hidden-layer ReLU perceptron of width 256.  In use its prediction is
-de-standardised, checked (envelope, residual, positivity), projected so that
+de-standardised, checked (envelope, overdraw, residual, positivity), projected so that
 the mass fractions keep their sum, and applied as one explicit update:
     Y_k += dt w_k / rho,  T += dt w_T / (rho c_p),  w_T = -sum_k dh_k w_k.
 
@@ -34,6 +34,10 @@ from oracle import oracle as O
 HIDDEN = 256
 RESID_TOL = 0.05
 POS_TOL = -1e-8
+CLIP_TOL = 0.05
+ENV_MARGIN = 0.01      # of the envelope's range
+ENV_MARGIN_SD = 0.05   # of the input's standard deviation
+Y_SD_FLOOR = 1e-4      # mass-fraction inputs
 
 
 def n_in(ns):
@@ -88,10 +92,13 @@ def sigma_floor(mu, sd):
 
 def fit_norm(X, Yt):
     """Mean and (floored, population) standard deviation of inputs and
-    targets, and the per-feature input envelope [min, max]."""
+    targets, and the per-feature input envelope [min, max].  The mass-fraction
+    inputs (features 2..) have their standard deviation floored at
+    Y_SD_FLOOR as well."""
     X, Yt = np.asarray(X, np.float64), np.asarray(Yt, np.float64)
     mx, my = X.mean(0), Yt.mean(0)
     sx = sigma_floor(mx, X.std(0))
+    sx[2:] = np.maximum(sx[2:], Y_SD_FLOOR)
     sy = sigma_floor(my, Yt.std(0))
     return {"mu_x": mx, "sd_x": sx, "mu_y": my, "sd_y": sy, "lo": X.min(0), "hi": X.max(0)}
 
@@ -117,25 +124,35 @@ def features(T, Y, p=1.0):
 
 
 def source(w, norm, setup, T, Y, p=1.0, emulate=True):
-    """Surrogate source for cells with state (T, Y [n, ns]).
+    """Surrogate source for cells with state (T, Y [n, ns]), dt = 1.
 
     Returns (omega [n, ns] after projection, omega_T [n], fallback [n] bool,
-    raw [n, ns] de-standardised prediction before projection).  Fallback:
-    any input outside the envelope, a residual |sum w|/(sum|w| + 1e-30) above
-    0.05 (before projection), or a mass fraction that the update would drive
-    below -1e-8."""
+    raw [n, ns] de-standardised prediction after the overdraw clip, before
+    the projection).  In order:
+      overdraw: raw_k < -rho Y_k is clipped to -rho Y_k; an excess beyond
+        CLIP_TOL sd_y[k] sends the cell to the exact path;
+      residual: |sum raw| > RESID_TOL (sum |raw| + sum_k sd_y[k]) -> exact;
+      projection: omega_k = raw_k - Y_k sum raw;
+      positivity: Y_k + omega_k / rho < POS_TOL for some k -> exact;
+      envelope: any input outside [lo - m, hi + m],
+        m = ENV_MARGIN (hi - lo) + ENV_MARGIN_SD sd_x -> exact."""
     X = features(T, Y, p)
     Yv = X[:, 2:]
     xhat = (X - norm["mu_x"]) / norm["sd_x"]
     raw = norm["mu_y"] + norm["sd_y"] * forward(w, xhat, emulate)
-    out_env = np.any((X < norm["lo"]) | (X > norm["hi"]), axis=1)
-    resid = np.abs(raw.sum(1)) / (np.abs(raw).sum(1) + 1e-30)
+    rho = np.array([O.eos(setup, t, y) for t, y in zip(X[:, 0], Yv)])
+    floor = -rho[:, None] * Yv
+    over = np.any(floor - raw > CLIP_TOL * norm["sd_y"], axis=1)
+    raw = np.maximum(raw, floor)
+    margin = (ENV_MARGIN * (np.asarray(norm["hi"]) - np.asarray(norm["lo"]))
+              + ENV_MARGIN_SD * np.asarray(norm["sd_x"]))
+    out_env = np.any((X < norm["lo"] - margin) | (X > norm["hi"] + margin), axis=1)
+    resid = np.abs(raw.sum(1)) > RESID_TOL * (np.abs(raw).sum(1) + np.sum(norm["sd_y"]))
     omega = raw - Yv * raw.sum(1, keepdims=True)
     dhf = np.asarray(setup["mech"]["dhf"], np.float64)
     omega_T = -(omega * dhf).sum(1)
-    rho = np.array([O.eos(setup, t, y) for t, y in zip(X[:, 0], Yv)])
     neg = np.any(Yv + omega / rho[:, None] < POS_TOL, axis=1)
-    return omega, omega_T, out_env | (resid > RESID_TOL) | neg, raw
+    return omega, omega_T, out_env | over | resid | neg, raw
 
 
 def apply(w, norm, setup, T, Y, p=1.0, emulate=True):

@@ -14,6 +14,8 @@ constexpr int MAXS = 16;
 constexpr int MAXR = 32;
 constexpr int BLOCK = 256;       // threads per workgroup: 4 wave64
 constexpr int DIAG_STRIDE = 32;  // doubles of partials per workgroup
+constexpr int FLAG_GROUP = 4 * BLOCK;  // FP64-island mask words per scan group
+constexpr int ISLAND_WG = 1024;        // workgroups (and diagnostics slots) of the island
 enum {
     DG_MASS = 0, DG_SP = 1, DG_ENTH = 17, DG_KIN = 18, DG_UMAX = 19, DG_TMIN = 20,
     DG_TMAX = 21, DG_NONFIN = 22, DG_TAUBAD = 23, DG_NEGY = 24, DG_FLAG = 25, DG_FALLBACK = 26,
@@ -270,6 +272,12 @@ struct StepArgs {
     int phase;            // PH_* mask
     int diag;             // write diagnostics partials
     int sur;              // FP32 surrogate mode: reactions left to the surrogate kernels
+    // FP32 mode: compaction of the cells flagged for the FP64 reaction step
+    int* woff;            // [nblocks * 4] offsets of the mask words within their group
+    int* gtot;            // [groups] flagged cells per group of mask words
+    int* list;            // [N] flagged cell indices in mask order
+    int* count;           // [1] number of listed cells
+    int P_nx, P_ny;       // grid extents (for the list kernel)
 };
 
 template <typename R>

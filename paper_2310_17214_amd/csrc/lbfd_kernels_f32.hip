@@ -40,12 +40,12 @@ int step_tile_h_f32(int dim, int nsm) {
     default: return tile_h_t<float, 16>(dim);
     }
 }
-hipError_t launch_island_f32(int dim, int nsm, const StepArgs<float>& a, int grid, hipStream_t s) {
+hipError_t launch_island_f32(int dim, int nsm, const StepArgs<float>& a, hipStream_t s) {
     switch (nsm) {
     case 0: return hipSuccess;
-    case 4: return launch_island_t<4>(dim, a, grid, s);
-    case 9: return launch_island_t<9>(dim, a, grid, s);
-    default: return launch_island_t<16>(dim, a, grid, s);
+    case 4: return launch_island_t<4>(dim, a, s);
+    case 9: return launch_island_t<9>(dim, a, s);
+    default: return launch_island_t<16>(dim, a, s);
     }
 }
 hipError_t launch_mlp_step_f32(int dim, int nsm, const StepArgs<float>& a, const SurWeights* gw,

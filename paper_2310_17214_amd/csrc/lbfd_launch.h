@@ -13,7 +13,8 @@ hipError_t launch_macro_f32(int dim, int nsm, const MacroArgs<float>& a, int gri
 hipError_t launch_macro_f64(int dim, int nsm, const MacroArgs<double>& a, int grid, hipStream_t s);
 hipError_t launch_init_f32(int dim, int nsm, const InitArgs<float>& a, int grid, hipStream_t s);
 hipError_t launch_init_f64(int dim, int nsm, const InitArgs<double>& a, int grid, hipStream_t s);
-hipError_t launch_island_f32(int dim, int nsm, const StepArgs<float>& a, int grid, hipStream_t s);
+// FP32 mode: compaction of the flagged cells and their FP64 reaction step
+hipError_t launch_island_f32(int dim, int nsm, const StepArgs<float>& a, hipStream_t s);
 // chemistry surrogate (FP32 only; species buckets 4, 9, 16)
 hipError_t launch_mlp_step_f32(int dim, int nsm, const StepArgs<float>& a, const SurWeights* gw,
                                const SurPar* sp, int grid, hipStream_t s);

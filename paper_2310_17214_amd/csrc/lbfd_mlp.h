@@ -41,9 +41,11 @@ struct SurPar {
     float mu_x[MLP_KIN], inv_sd_x[MLP_KIN], lo[MLP_KIN], hi[MLP_KIN];
     float mu_y[MLP_OUT], sd_y[MLP_OUT];
     float p_in;        // the constant thermodynamic-pressure input
-    float resid_tol;   // |sum w| / (sum |w| + 1e-30) above this -> exact fallback
-    float pos_tol;     // Y_k + dt w_k / rho below this -> exact fallback
-    float pad2;
+    float resid_tol;   // |sum w| / (sum |w| + sd_sum) above this -> exact fallback
+    float pos_tol;     // Y_k + dt w_k / rho below this (after the update) -> exact fallback
+    float sd_sum;      // sum_k sd_y[k]: the residual's scale floor
+    float clip_tol;    // overdraw of a species beyond clip_tol * sd_y[k] -> exact fallback
+    float pad3[3];
 };
 
 // K order of the first layer: lane half h holds input features 8h..8h+7.

@@ -29,7 +29,9 @@ struct HostMech {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, parf, pard, scratch, red, sw, sp, total;
+    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, woff, gtot, list, count, parf, pard,
+        scratch, red, sw, sp, total;
+    int nslots;                   // diagnostics slots: step tiles, then island workgroups
     int nbx, nby, zc, nblocks, grid;  // step kernel: 64 x TH tiles of one plane,
                                       // grid padded to a multiple of the 8 XCDs
     int nlin;                     // one-cell-per-thread kernels
@@ -67,8 +69,14 @@ Layout make_layout(const lbfd_grid& gr) {
     L.Y1 = take((size_t)nsm_bucket(gr.n_species) * N * s);
     L.divu = take(N * s);
     L.phi = take(N * s);
-    L.part = take((size_t)L.nblocks * DIAG_STRIDE * sizeof(double));
-    L.flags = take((size_t)L.nblocks * (BLOCK / 64) * sizeof(unsigned long long));
+    L.nslots = L.nblocks + ISLAND_WG;
+    L.part = take((size_t)L.nslots * DIAG_STRIDE * sizeof(double));
+    const size_t nwords = (size_t)L.nblocks * (BLOCK / 64);
+    L.flags = take(nwords * sizeof(unsigned long long));
+    L.woff = take(nwords * sizeof(int));
+    L.gtot = take((nwords + FLAG_GROUP - 1) / FLAG_GROUP * sizeof(int));
+    L.list = take(N * sizeof(int));
+    L.count = take(sizeof(int));
     L.parf = take(sizeof(Par<float>));
     L.pard = take(sizeof(Par<double>));
     L.scratch = take(5 * N * sizeof(double));
@@ -359,6 +367,12 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.phase = phase;
     a.diag = 1;
     a.sur = sizeof(R) == 4 && c->sur && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM);
+    a.woff = dptr<int>(c, c->L.woff);
+    a.gtot = dptr<int>(c, c->L.gtot);
+    a.list = dptr<int>(c, c->L.list);
+    a.count = dptr<int>(c, c->L.count);
+    a.P_nx = c->grid.nx;
+    a.P_ny = c->grid.ny;
     hipError_t e;
     if ((e = time_mark(c, LBFD_KERNEL_STEP, false)) != hipSuccess)
         return hip_check(c, e, "timing event");
@@ -376,9 +390,11 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
                                         std::min(c->n_cu, c->L.nblocks), c->stream);
             if (e == hipSuccess) e = time_mark(c, LBFD_KERNEL_SURROGATE, true);
         }
-        if (e == hipSuccess && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM)) {
+        // every FP32 step with species runs the island (an empty list when no
+        // cell is flagged), so that its diagnostics slots describe this step
+        if (e == hipSuccess && c->ns > 0) {
             e = time_mark(c, LBFD_KERNEL_ISLAND, false);
-            if (e == hipSuccess) e = launch_island_f32(c->dim, c->nsm, a, c->L.grid, c->stream);
+            if (e == hipSuccess) e = launch_island_f32(c->dim, c->nsm, a, c->stream);
             if (e == hipSuccess) e = time_mark(c, LBFD_KERNEL_ISLAND, true);
         }
     }
@@ -613,7 +629,7 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
     st = c->fp32 ? launch_init<float>(c, u != nullptr) : launch_init<double>(c, u != nullptr);
     if (st) return st;
     st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.part), 0,
-                                     (size_t)c->L.nblocks * DIAG_STRIDE * sizeof(double), c->stream),
+                                     (size_t)c->L.nslots * DIAG_STRIDE * sizeof(double), c->stream),
                    "clear diagnostics");
     if (st) return st;
     st = hip_check(c, hipStreamSynchronize(c->stream), "init");
@@ -723,7 +739,8 @@ lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
     if (st) return st;
     double* red = dptr<double>(c, c->L.red);
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(BLOCK), 0, c->stream,
-                       dptr<double>(c, c->L.part), c->L.nblocks, c->ns, red);
+                       dptr<double>(c, c->L.part),
+                       (c->fp32 && c->ns > 0) ? c->L.nslots : c->L.nblocks, c->ns, red);
     if ((st = hip_check(c, hipGetLastError(), "diagnostics launch"))) return st;
     double h[DG_COUNT];
     st = hip_check(c, hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, c->stream),
@@ -836,16 +853,26 @@ lbfd_status lbfd_set_surrogate(lbfd_ctx* c, const float* w, const float* norm, c
             return fail(c, LBFD_E_INVAL, "input standard deviation must be positive");
         P.mu_x[i] = norm[i];
         P.inv_sd_x[i] = 1.f / sd;
-        P.lo[i] = env[i];
-        P.hi[i] = env[ni + i];
+        // the training envelope, widened on both sides by 1 % of its range
+        // plus 0.05 standard deviations of the input
+        const float margin = 0.01f * (env[ni + i] - env[i]) + 0.05f * sd;
+        if (!(margin >= 0.f)) return fail(c, LBFD_E_INVAL, "envelope with hi < lo");
+        P.lo[i] = env[i] - margin;
+        P.hi[i] = env[ni + i] + margin;
     }
+    double sd_sum = 0.0;
     for (int o = 0; o < no; ++o) {
         P.mu_y[o] = norm[2 * ni + o];
         P.sd_y[o] = norm[2 * ni + no + o];
+        if (!(P.sd_y[o] > 0.f) || !std::isfinite(P.mu_y[o]))
+            return fail(c, LBFD_E_INVAL, "output standard deviation must be positive");
+        sd_sum += P.sd_y[o];
     }
     P.p_in = 1.f;
     P.resid_tol = 0.05f;
     P.pos_tol = -1e-8f;
+    P.sd_sum = (float)sd_sum;
+    P.clip_tol = 0.05f;
     lbfd_status st = set_device(c);
     if (st) return st;
     if ((st = hip_check(c, hipMemcpyAsync(c->ws + c->L.sw, &S, sizeof(S), hipMemcpyHostToDevice,

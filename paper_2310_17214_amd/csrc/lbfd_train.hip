@@ -49,7 +49,8 @@ __device__ __forceinline__ float bf16_float(u16 b) {
 
 // ------------------------------------------------------------ statistics
 // One workgroup per column (inputs first, then targets): FP64 mean, then
-// population standard deviation (floored at 1e-12 max(|mu|, 1)), min, max.
+// population standard deviation (floored at 1e-12 max(|mu|, 1), and at 1e-4
+// for the mass-fraction inputs), min, max.
 __global__ __launch_bounds__(TB) void norm_fit_kernel(const float* __restrict__ x,
                                                       const float* __restrict__ y, int n, int ni,
                                                       int no, TrainNorm* __restrict__ out) {
@@ -89,6 +90,9 @@ __global__ __launch_bounds__(TB) void norm_fit_kernel(const float* __restrict__ 
     if (t == 0) {
         double sd = sqrt(s1[0] / (double)n);
         sd = fmax(sd, 1e-12 * fmax(fabs(mu), 1.0));
+        // mass-fraction inputs: species that stay below ~1e-4 are seen as
+        // near-constant inputs rather than amplified by a tiny spread
+        if (isx && c >= 2) sd = fmax(sd, 1e-4);
         if (isx) {
             out->mu_x[c] = (float)mu;
             out->sd_x[c] = (float)sd;

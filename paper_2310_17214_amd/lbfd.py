@@ -218,6 +218,7 @@ class Context:
         self._check(L.lbfd_create(C.byref(self._grid), C.c_void_p(self._ptr), nbytes.value,
                                   C.c_void_p(self.stream.cuda_stream), C.byref(h)), None)
         self._h = h
+        self._lib = L
         self._check(L.lbfd_set_phase_field(h, _f64(phi).ctypes.data_as(_dp)))
         if self.ns > 0:
             self._mech = _MechArrays(setup)
@@ -232,12 +233,14 @@ class Context:
             raise LbfdError(status, msg)
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h:
+        # the library handle is kept on the object: module globals may already
+        # be gone when this runs at interpreter exit
+        h, L = getattr(self, "_h", None), getattr(self, "_lib", None)
+        if h and L is not None:
             try:
-                lib().lbfd_synchronize(h)
+                L.lbfd_synchronize(h)
             finally:
-                lib().lbfd_destroy(h)
+                L.lbfd_destroy(h)
             self._h = None
 
     def init_state(self, T, Y=None, u=None):
@@ -380,15 +383,16 @@ class Trainer:
         if st != LBFD_OK:
             raise LbfdError(st, "trainer create")
         self._h = h
+        self._lib = L
 
     def _check(self, st):
         if st != LBFD_OK:
             raise LbfdError(st, lib().lbfd_trainer_last_error(self._h).decode())
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h:
-            lib().lbfd_trainer_destroy(h)
+        h, L = getattr(self, "_h", None), getattr(self, "_lib", None)
+        if h and L is not None:
+            L.lbfd_trainer_destroy(h)
             self._h = None
 
     def fit_norm(self, x, y):

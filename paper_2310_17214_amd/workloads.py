@@ -553,6 +553,26 @@ def cfg3_bed(nx=384, ny=192, nz=192, precision="fp32", seed=3, bed=(48, 336), x_
     return wl
 
 
+def cfg4_bed(nx=256, ny=128, nz=128, precision="fp32", seed=2, bed=(32, 224), x_split=96,
+             porosity=0.40, r=8.0, steps=5000, mech_seed=33, T_burnt=1100.0) -> Workload:
+    """The sphere bed of cfg2 (grid, particles, flow, heat exchange) with the
+    synthetic 9-species / 21-reversible-reaction mechanism: the workload of
+    the chemistry surrogate."""
+    mech = mech_synthetic9(seed=mech_seed)
+    s = _reactive_bed_setup(3, nx, ny, nz, mech, SYNTH9_Y_IN, precision, T_s=700.0,
+                            nu_in=0.008, u_in=0.005, transport=0, Le=[1.0] * 9,
+                            n_sub=int(mech["n_sub"]))
+    shape = (nz, ny, nx)
+    parts = sphere_bed(shape, bed, r, porosity, seed)
+    phi = bed_phi(shape, parts, s["eta"], (False, True, True))
+    T0, Y0 = _split_init(shape, phi, x_split, T_IN, SYNTH9_Y_IN, T_burnt, burnt_synth9(),
+                         s["T_s"])
+    wl = Workload(f"cfg4_sphere_bed_9species_d3q19_{nx}x{ny}x{nz}", s, phi, T0, Y0, None, steps)
+    wl.particles = parts
+    wl.bed = bed
+    return wl
+
+
 # ----------------------------------------------------- small test setups
 
 def periodic_box(dim, n, ns=0, precision="fp64"):
