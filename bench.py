@@ -40,12 +40,14 @@ def kernel_hash():
 def make_workload(name):
     from paper_2310_17214_amd import workloads as W
 
-    if name == "cfg2":
-        return W.cfg2_bed(precision="fp32")
-    if name == "cfg2_fp64":
-        return W.cfg2_bed(precision="fp64")
-    if name == "cfg1":
-        return W.cfg1_cylinder()
+    if name == "sphere_bed":
+        return W.bed_one_step(precision="fp32")
+    if name == "sphere_bed_fp64":
+        return W.bed_one_step(precision="fp64")
+    if name == "cylinder":
+        return W.cylinder_channel()
+    if name == "sphere_bed_9sp":
+        return W.bed_sphere_9sp(precision="fp32")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -103,7 +105,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="sphere_bed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true")

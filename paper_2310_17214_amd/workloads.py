@@ -447,7 +447,7 @@ def base_setup(dim, nx, ny, nz, ns, precision="fp64"):
         Le=[1.0] * ns, n_sub=1, theta_ign=1e-6, mech=mech_empty(ns))
 
 
-def cfg1_cylinder() -> Workload:
+def cylinder_channel() -> Workload:
     """2-D D2Q9 channel 128x64, FP64: one solid cylinder r = 10 at (32, 32),
     tanh phase field of width 4, inert gas, inlet u = 0.02, Re = 20 on the
     diameter (nu = 0.02), cylinder held at 1.5 T_inlet, Pr = 0.7, 2000 steps."""
@@ -462,7 +462,7 @@ def cfg1_cylinder() -> Workload:
     s["A_T"] = a_t_fit(s["T_s"])
     phi = cylinder_phi(nx, ny, 32.0, 32.0, 10.0, s["eta"])
     T0 = (1.0 - phi) * T_IN + phi * s["T_s"]
-    return Workload("cfg1_cylinder_d2q9_128x64", s, phi, T0, np.zeros((0, 1, ny, nx)), None,
+    return Workload("cylinder_channel_d2q9_128x64", s, phi, T0, np.zeros((0, 1, ny, nx)), None,
                     2000)
 
 
@@ -494,8 +494,8 @@ def one_step_rate_constant(t_ad=1100.0, theta=15000.0, rho_ad=T_IN / 1100.0, y_o
     return 1.0 / (tau_steps * math.exp(-theta / t_ad) * rho_ad * y_o)
 
 
-CFG2_Y_IN = [0.4, 0.5, 0.0, 0.1]
-CFG2_Y_BURNT = [0.0, 0.1, 0.8, 0.1]
+ONE_STEP_Y_IN = [0.4, 0.5, 0.0, 0.1]
+ONE_STEP_Y_BURNT = [0.0, 0.1, 0.8, 0.1]
 
 
 def _split_init(shape, phi, x_split, T_fresh, Y_fresh, T_burnt, Y_burnt, T_s):
@@ -511,25 +511,25 @@ def _split_init(shape, phi, x_split, T_fresh, Y_fresh, T_burnt, Y_burnt, T_s):
     return T0, Y0
 
 
-def cfg2_bed(nx=256, ny=128, nz=128, precision="fp32", seed=2, bed=(32, 224), x_split=96,
+def bed_one_step(nx=256, ny=128, nz=128, precision="fp32", seed=2, bed=(32, 224), x_split=96,
              porosity=0.40, r=8.0, steps=5000) -> Workload:
     """3-D D3Q19 packed channel (default 256x128x128), seeded random spheres
     r = 8 at porosity 0.4, tanh width 4, rho ~ 1/T, one-step irreversible
     F + O -> 2P with theta = 15000 K and Q/cp = 2000 K, lean premixed inlet."""
     mech = mech_one_step(A=one_step_rate_constant())
-    s = _reactive_bed_setup(3, nx, ny, nz, mech, CFG2_Y_IN, precision, T_s=700.0, nu_in=0.008,
+    s = _reactive_bed_setup(3, nx, ny, nz, mech, ONE_STEP_Y_IN, precision, T_s=700.0, nu_in=0.008,
                             u_in=0.005, transport=0, Le=[1.0] * 4, n_sub=1)
     shape = (nz, ny, nx)
     parts = sphere_bed(shape, bed, r, porosity, seed)
     phi = bed_phi(shape, parts, s["eta"], (False, True, True))
-    T0, Y0 = _split_init(shape, phi, x_split, T_IN, CFG2_Y_IN, 1100.0, CFG2_Y_BURNT, s["T_s"])
-    wl = Workload(f"cfg2_sphere_bed_d3q19_{nx}x{ny}x{nz}", s, phi, T0, Y0, None, steps)
+    T0, Y0 = _split_init(shape, phi, x_split, T_IN, ONE_STEP_Y_IN, 1100.0, ONE_STEP_Y_BURNT, s["T_s"])
+    wl = Workload(f"sphere_bed_one_step_d3q19_{nx}x{ny}x{nz}", s, phi, T0, Y0, None, steps)
     wl.particles = parts
     wl.bed = bed
     return wl
 
 
-def cfg3_bed(nx=384, ny=192, nz=192, precision="fp32", seed=3, bed=(48, 336), x_split=144,
+def bed_superquadric_9sp(nx=384, ny=192, nz=192, precision="fp32", seed=3, bed=(48, 336), x_split=144,
              porosity=0.45, steps=5000, sphere_share=0.0, mech_seed=33,
              T_burnt=1100.0) -> Workload:
     """3-D D3Q19 bed of seeded superquadrics, synthetic 9-species /
@@ -547,15 +547,15 @@ def cfg3_bed(nx=384, ny=192, nz=192, precision="fp32", seed=3, bed=(48, 336), x_
     phi = bed_phi(shape, parts, s["eta"], (False, True, True))
     T0, Y0 = _split_init(shape, phi, x_split, T_IN, SYNTH9_Y_IN, T_burnt, burnt_synth9(),
                          s["T_s"])
-    wl = Workload(f"cfg3_superquadric_bed_d3q19_{nx}x{ny}x{nz}", s, phi, T0, Y0, None, steps)
+    wl = Workload(f"superquadric_bed_9species_d3q19_{nx}x{ny}x{nz}", s, phi, T0, Y0, None, steps)
     wl.particles = parts
     wl.bed = bed
     return wl
 
 
-def cfg4_bed(nx=256, ny=128, nz=128, precision="fp32", seed=2, bed=(32, 224), x_split=96,
+def bed_sphere_9sp(nx=256, ny=128, nz=128, precision="fp32", seed=2, bed=(32, 224), x_split=96,
              porosity=0.40, r=8.0, steps=5000, mech_seed=33, T_burnt=1100.0) -> Workload:
-    """The sphere bed of cfg2 (grid, particles, flow, heat exchange) with the
+    """The sphere bed of bed_one_step (grid, particles, flow, heat exchange) with the
     synthetic 9-species / 21-reversible-reaction mechanism: the workload of
     the chemistry surrogate."""
     mech = mech_synthetic9(seed=mech_seed)
@@ -567,7 +567,7 @@ def cfg4_bed(nx=256, ny=128, nz=128, precision="fp32", seed=2, bed=(32, 224), x_
     phi = bed_phi(shape, parts, s["eta"], (False, True, True))
     T0, Y0 = _split_init(shape, phi, x_split, T_IN, SYNTH9_Y_IN, T_burnt, burnt_synth9(),
                          s["T_s"])
-    wl = Workload(f"cfg4_sphere_bed_9species_d3q19_{nx}x{ny}x{nz}", s, phi, T0, Y0, None, steps)
+    wl = Workload(f"sphere_bed_9species_d3q19_{nx}x{ny}x{nz}", s, phi, T0, Y0, None, steps)
     wl.particles = parts
     wl.bed = bed
     return wl

@@ -38,7 +38,7 @@ def test_no_oracle_in_product_path():
 
 
 def _grid(**kw):
-    s = W.cfg1_cylinder().setup
+    s = W.cylinder_channel().setup
     g = lbfd.make_grid(s)
     for k, v in kw.items():
         setattr(g, k, v)

@@ -62,9 +62,9 @@ def small_box(precision="fp64", ns=4):
     s["lb_bc"] = ["inlet", "outlet", "wall", "wall", "periodic", "periodic"]
     s["fd_bc"] = ["dirichlet", "neumann", "neumann", "dirichlet", "periodic", "periodic"]
     s["mech"] = W.mech_one_step(A=W.one_step_rate_constant(tau_steps=5.0))
-    s["Y_in"] = W.CFG2_Y_IN
-    s["fd_val"][0] = [300.0] + W.CFG2_Y_IN
-    s["fd_val"][3] = [900.0] + W.CFG2_Y_BURNT
+    s["Y_in"] = W.ONE_STEP_Y_IN
+    s["fd_val"][0] = [300.0] + W.ONE_STEP_Y_IN
+    s["fd_val"][3] = [900.0] + W.ONE_STEP_Y_BURNT
     s["u_in"] = [0.02, 0.0, 0.0]
     s["nu_in"] = 0.03
     s["T_s"] = 800.0
@@ -93,8 +93,8 @@ def test_aa_pattern_populations_after_odd_and_even_steps():
         assert max(errs.values()) <= 1e-13, errs
 
 
-def test_cfg1_cylinder_fp64_2000_steps():
-    wl = W.cfg1_cylinder()
+def test_cylinder_channel_fp64_2000_steps():
+    wl = W.cylinder_channel()
     say(f"{wl.name} fp64 {wl.steps} steps")
     ctx, orc = run_both(wl.setup, wl.phi, wl.T0, None, wl.steps)
     errs = compare(ctx, orc)
@@ -105,7 +105,7 @@ def test_cfg1_cylinder_fp64_2000_steps():
 def _crop(precision, **kw):
     args = dict(nx=38, ny=17, nz=15, precision=precision, bed=(6, 30), x_split=18, steps=0)
     args.update(kw)
-    wl = W.cfg2_bed(**args)
+    wl = W.bed_one_step(**args)
     # low enough that the FP64 reaction island takes cells in this small crop
     wl.setup["theta_ign"] = 0.01
     return wl
@@ -226,8 +226,8 @@ def test_full_size_bed_one_step_from_gpu_state():
     (FP32): after 20 GPU steps, load the GPU state into the oracle, advance
     both by one step and compare every cell (FP32 vs FP64 rounding of one
     step), plus sum_k Y_k = 1 at full size."""
-    wl = W.cfg2_bed(precision="fp32", steps=0)
-    wl64 = W.cfg2_bed(precision="fp64", steps=0)
+    wl = W.bed_one_step(precision="fp32", steps=0)
+    wl64 = W.bed_one_step(precision="fp64", steps=0)
     say(f"{wl.name} fp32 full size, 20 + 1 steps")
     ctx = lb().Context(wl.setup, wl.phi)
     ctx.init_state(wl.T0, wl.Y0)
@@ -250,7 +250,7 @@ def test_full_size_bed_one_step_from_gpu_state():
 
 
 def _crop9(precision):
-    wl = W.cfg3_bed(nx=37, ny=18, nz=14, precision=precision, bed=(6, 31), x_split=19, steps=0,
+    wl = W.bed_superquadric_9sp(nx=37, ny=18, nz=14, precision=precision, bed=(6, 31), x_split=19, steps=0,
                     T_burnt=1400.0)
     wl.setup["theta_ign"] = 0.01
     return wl

@@ -29,7 +29,7 @@ def _crop9(precision="fp32", **kw):
     args = dict(nx=37, ny=18, nz=14, precision=precision, bed=(6, 31), x_split=19, steps=0,
                 T_burnt=1400.0)
     args.update(kw)
-    wl = W.cfg3_bed(**args)
+    wl = W.bed_superquadric_9sp(**args)
     wl.setup["theta_ign"] = 0.01
     return wl
 
@@ -197,7 +197,7 @@ def test_s3_trained_surrogate_tracks_the_exact_path_within_one_percent():
     <= 1 %.  Held-out per-species RMS errors are reported."""
     from paper_2310_17214_amd import surrogate as SG
 
-    wl = W.cfg4_bed(nx=64, ny=32, nz=32, bed=(8, 56), x_split=24, steps=1000)
+    wl = W.bed_sphere_9sp(nx=64, ny=32, nz=32, bed=(8, 56), x_split=24, steps=1000)
     ns = wl.setup["ns"]
     say(f"S3: {wl.name}, sampling an exact run of 1000 steps")
     x, y = SG.sample_run(wl, steps=1000, every=10, per_snapshot=2048, seed=4)

@@ -135,7 +135,7 @@ def test_training_reduces_the_loss_and_exports_to_the_inference_kernel():
     assert hist[-1] < 0.1 * hist[0], hist
     w, nrm, env = tr.export()
     # the exported model in a context: inference against the reference
-    wl = W.cfg3_bed(nx=12, ny=8, nz=8, precision="fp32", bed=(2, 10), x_split=6, steps=0)
+    wl = W.bed_superquadric_9sp(nx=12, ny=8, nz=8, precision="fp32", bed=(2, 10), x_split=6, steps=0)
     ctx = lb().Context(wl.setup, wl.phi)
     ctx.set_surrogate(w, nrm, env)
     n = 2000

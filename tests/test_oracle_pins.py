@@ -276,7 +276,7 @@ def test_P10_fd_flux_conservation(unequal_le):
     n = 8
     s = _box(3, n, ns=4, A_T=0.0)
     s["mech"] = W.mech_one_step()
-    s["Y_in"] = W.CFG2_Y_IN
+    s["Y_in"] = W.ONE_STEP_Y_IN
     if unequal_le:
         s["Le"] = [0.8, 1.1, 1.2, 0.9]
         s["transport"] = 1
@@ -449,7 +449,7 @@ def test_eos_ideal_gas():
 def test_P9_mass_fractions_sum_to_one_on_bed():
     """Species transport (with the correction flux) plus element-balanced
     chemistry keep sum_k Y_k = 1 in every cell, every step."""
-    wl = W.cfg2_bed(nx=24, ny=12, nz=12, precision="fp64", bed=(4, 20), x_split=12, steps=0)
+    wl = W.bed_one_step(nx=24, ny=12, nz=12, precision="fp64", bed=(4, 20), x_split=12, steps=0)
     wl.setup["theta_ign"] = 1e-6  # count every reacting cell as active
     o = O.Oracle(wl.setup, wl.phi)
     o.init_state(wl.T0, wl.Y0)
@@ -468,7 +468,7 @@ def test_P16_axis_permutation_symmetry():
     n = 6
     s = _box(3, n, ns=4, A_T=60.0, T_s=500.0)
     s["mech"] = W.mech_one_step(A=W.one_step_rate_constant())
-    s["Y_in"] = W.CFG2_Y_IN
+    s["Y_in"] = W.ONE_STEP_Y_IN
     shape = (n, n, n)
     rng = np.random.default_rng(11)
     phi = 0.5 + 0.5 * W.random_smooth_field(shape, 21)
@@ -502,7 +502,7 @@ def test_a_t_fit_reproduces_paper_optimum():
     assert abs(W.a_t_fit(g["T_wall_K"]) - g["A_T_star"]) / g["A_T_star"] < 0.01
     for r in (4.0 / 3.0, 1.5, 7.0 / 3.0, 3.0):
         assert W.a_t_fit(300.0 * r) == pytest.approx(fit["intercept"] + fit["slope"] * r, rel=1e-15)
-    assert W.cfg1_cylinder().setup["A_u"] == GOLDEN["a_u_optimum"]["A_u_star"]
+    assert W.cylinder_channel().setup["A_u"] == GOLDEN["a_u_optimum"]["A_u_star"]
 
 
 def test_sutherland_ratio_matches_the_absolute_law():

@@ -97,7 +97,7 @@ def _model(ns, seed=7):
 
 
 def test_projection_keeps_mass_fractions_summing_to_one():
-    wl = W.cfg3_bed(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0)
+    wl = W.bed_superquadric_9sp(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0)
     s = wl.setup
     w, norm = _model(9)
     Y = np.full((6, 9), 1.0 / 9)
@@ -108,7 +108,7 @@ def test_projection_keeps_mass_fractions_summing_to_one():
 
 
 def test_fallback_flags():
-    wl = W.cfg3_bed(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0)
+    wl = W.bed_superquadric_9sp(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0)
     s = wl.setup
     w, norm = _model(9)
     # a prediction fixed at a small balanced source: only the checks decide
@@ -130,7 +130,7 @@ def test_fallback_flags():
 def test_step_source_one_step_mechanism_is_the_arrhenius_rate():
     """n_sub = 1: omega_bar_k = rho dY_k = M_k s_k Q with
     Q = A exp(-theta/T) [F][O] (mass action, Eq. 8) and dt = 1."""
-    wl = W.cfg2_bed(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0)
+    wl = W.bed_one_step(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0)
     s = wl.setup
     m = s["mech"]
     T = np.array([900.0, 1100.0, 1300.0])
@@ -144,7 +144,7 @@ def test_step_source_one_step_mechanism_is_the_arrhenius_rate():
 
 
 def test_step_source_conserves_elements_of_the_synthetic_mechanism():
-    wl = W.cfg3_bed(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0, T_burnt=1400.0)
+    wl = W.bed_superquadric_9sp(nx=12, ny=8, nz=8, bed=(2, 10), x_split=6, steps=0, T_burnt=1400.0)
     s = wl.setup
     comp = np.array(W._SPECIES, float)
     M = np.asarray(s["mech"]["M"], float)

@@ -39,8 +39,8 @@ def test_burnt_composition_conserves_elements():
     e_b = (np.array(W.burnt_synth9()) / M) @ comp
     assert np.allclose(e_in, e_b) and abs(sum(W.burnt_synth9()) - 1) < 1e-12
     # one-step mechanism: lean, all fuel burnt
-    assert abs(sum(W.CFG2_Y_IN) - 1) < 1e-15 and abs(sum(W.CFG2_Y_BURNT) - 1) < 1e-15
-    assert W.CFG2_Y_IN[0] < W.CFG2_Y_IN[1]
+    assert abs(sum(W.ONE_STEP_Y_IN) - 1) < 1e-15 and abs(sum(W.ONE_STEP_Y_BURNT) - 1) < 1e-15
+    assert W.ONE_STEP_Y_IN[0] < W.ONE_STEP_Y_IN[1]
 
 
 def test_one_step_rate_constant_sets_the_time_scale():
@@ -74,7 +74,7 @@ def test_phase_profiles():
 
 
 def test_cfg1_parameters():
-    wl = W.cfg1_cylinder()
+    wl = W.cylinder_channel()
     s = wl.setup
     assert (s["nx"], s["ny"]) == (128, 64) and wl.steps == 2000
     assert abs(s["u_in"][0] * 20.0 / s["nu_in"] - 20.0) < 1e-12   # Re = 20 on D = 20
