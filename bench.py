@@ -11,7 +11,11 @@ synchronisation, timed with HIP events on the stream the kernels run on.
 A second pass of K steps brackets every step-kernel launch with HIP events:
 their mean is the kernel duration the roofline figure divides by.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+The same line carries the chemistry surrogate against exact chemistry on the
+9-species sphere bed: ms per step of both paths, their ratio, and the maximum
+relative temperature difference after 1000 steps from the same state.
+
+Prints one JSON line.  --gpus above 1 is refused: this runs on one GPU.
 """
 import argparse
 import hashlib
@@ -19,6 +23,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -86,6 +92,76 @@ def cpu_baseline(wl, target_s=15.0):
                       f"{wl.setup['nz']} grid from the initial state, {dt:.1f} s"}
 
 
+MLP_FLOP_PER_CELL = 2 * (11 * 256 + 256 * 256 + 256 * 9)   # 141,312 (9 species)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_measure(steps=200, seed=4, log=None):
+    """Surrogate against exact chemistry on the 9-species sphere bed
+    (256x128x128): train on pairs sampled from an exact run (every 25th step
+    of 5000, 10,000 cells each, 90/10 split), then time both paths and compare
+    T after 1000 steps from the same initial state."""
+    import torch
+
+    from paper_2310_17214_amd import lbfd, surrogate as SG, workloads as W
+
+    t0 = time.perf_counter()
+    wl = W.bed_sphere_9sp(precision="fp32")
+    ns = wl.setup["ns"]
+    x, y = SG.sample_run(wl, steps=5000, every=25, per_snapshot=10000, seed=seed)
+    t_sample = time.perf_counter() - t0
+    (xt, yt), (xh, yh) = SG.split(x, y, 0.1, seed=seed + 1)
+    t1 = time.perf_counter()
+    w, nrm, env, losses = SG.train(xt, yt, ns, epochs=6, batch=8192, seed=seed + 2, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    res = {}
+    for mode in ("exact", "surrogate"):
+        ctx = lbfd.Context(wl.setup, wl.phi)
+        if mode == "surrogate":
+            ctx.set_surrogate(w, nrm, env)
+            rmse, rel, fb_ho = SG.heldout_rmse(ctx, xh, yh)
+        ctx.init_state(wl.T0, wl.Y0)
+        ctx.step(20)
+        ctx.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.step(steps)
+        e1.record(ctx.stream)
+        ctx.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ctx.set_timing(True)
+        ctx.step(steps)
+        kt = {k: ctx.kernel_time(i) for i, k in enumerate(("step", "island", "mlp"))}
+        ctx.set_timing(False)
+        ctx.step(1000 - 20 - 2 * steps)
+        d = ctx.diagnostics()
+        res[mode] = {"ms": ms, "kt": kt, "T": ctx.fields()["T"], "diag": d}
+    ex, su = res["exact"], res["surrogate"]
+    err = float(np.max(np.abs(su["T"] - ex["T"]) / ex["T"]))
+    mlp_ms = su["kt"]["mlp"][1]
+    tflops = MLP_FLOP_PER_CELL * wl.cells / (mlp_ms * 1e-3) / 1e12
+    return {
+        "workload": wl.name, "species": ns, "reactions": len(wl.setup["mech"]["A"]),
+        "n_sub": int(wl.setup["n_sub"]),
+        "exact_ms_per_step": round(ex["ms"], 5), "surrogate_ms_per_step": round(su["ms"], 5),
+        "speedup": round(ex["ms"] / su["ms"], 4),
+        "max_rel_T_err_1000_steps": err, "T_err_bar": 0.01,
+        "fallback_share": su["diag"]["n_fallback"] / (1000.0 * wl.cells),
+        "kernels_ms": {"exact": {k: round(v[1], 5) for k, v in ex["kt"].items()},
+                       "surrogate": {k: round(v[1], 5) for k, v in su["kt"].items()}},
+        "mlp_roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / BF16_PEAK_TFLOPS, 4),
+                         "flop_per_cell": MLP_FLOP_PER_CELL},
+        "training": {"pairs": int(x.shape[0]), "train_pairs": int(xt.shape[0]),
+                     "sample_s": round(t_sample, 2), "train_s": round(t_train, 2),
+                     "epochs": len(losses), "final_loss": losses[-1]},
+        "heldout_rel_rmse": [None if not np.isfinite(v) else round(float(v), 5) for v in rel],
+        "heldout_fallback_share": fb_ho,
+    }
+
+
 def copy_probe():
     """A plain device copy of 1 GiB, run under the HBM counters to calibrate
     FETCH_SIZE / WRITE_SIZE."""
@@ -109,10 +185,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on one GPU "
-              "(multi-GPU slab decomposition is design-only)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: the benchmark runs on one GPU "
+              "(the slab decomposition over several GPUs is described, not built)",
+              file=sys.stderr)
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
@@ -185,6 +263,10 @@ def main():
                         "n_nonfinite": diag["n_nonfinite"]},
         "wall_s": round(wall, 3),
     }
+    if not args.no_surrogate:
+        print("bench: surrogate vs exact chemistry (9-species bed)", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate_measure(
+            log=lambda m: print("bench:", m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
