@@ -22,7 +22,9 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 UNITS = [
-    ("lbfd_kernels_f32.hip", []),
+    # matrix-product accumulators in ordinary VGPRs (the surrogate kernels'
+    # epilogues read them directly)
+    ("lbfd_kernels_f32.hip", ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
     ("lbfd_kernels_f64.hip", ["-ffp-contract=off"]),
     ("lbfd_runtime.hip", []),
     ("lbfd_train.hip", []),

@@ -387,7 +387,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
             if (e == hipSuccess)
                 e = launch_mlp_step_f32(c->dim, c->nsm, a, dptr<SurWeights>(c, c->L.sw),
                                         dptr<SurPar>(c, c->L.sp),
-                                        std::min(c->n_cu, c->L.nblocks), c->stream);
+                                        std::min(c->n_cu, (c->L.nblocks + 1) / 2), c->stream);
             if (e == hipSuccess) e = time_mark(c, LBFD_KERNEL_SURROGATE, true);
         }
         // every FP32 step with species runs the island (an empty list when no
