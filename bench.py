@@ -162,6 +162,32 @@ def surrogate_measure(steps=200, seed=4, log=None):
     }
 
 
+def mlp_probe(steps):
+    """The in-step surrogate alone on the 9-species sphere bed (freshly
+    initialised weights: the kernel's work does not depend on them), for
+    counter runs; prints the surrogate kernel's mean launch time."""
+    import torch  # noqa: F401
+
+    from paper_2310_17214_amd import lbfd, surrogate as SG, workloads as W
+
+    wl = W.bed_sphere_9sp(precision="fp32")
+    ns = wl.setup["ns"]
+    ni = ns + 2
+    w = SG.initial_weights(ns, 1)
+    norm = np.concatenate([[700.0, 1.0] + [0.1] * ns, [300.0, 1e-12] + [0.1] * ns,
+                           [0.0] * ns, [1e-3] * ns]).astype(np.float32)
+    env = np.concatenate([[0.0, 1.0] + [0.0] * ns, [5000.0, 1.0] + [1.0] * ns]).astype(np.float32)
+    assert len(norm) == 2 * ni + 2 * ns and len(env) == 2 * ni
+    ctx = lbfd.Context(wl.setup, wl.phi)
+    ctx.set_surrogate(w, norm, env)
+    ctx.init_state(wl.T0, wl.Y0)
+    ctx.set_timing(True)
+    ctx.step(steps)
+    n, ms = ctx.kernel_time(lbfd.LBFD_KERNEL_SURROGATE)
+    print(json.dumps({"mlp_probe_steps": steps, "mlp_kernel_ms": ms,
+                      "tflops": MLP_FLOP_PER_CELL * wl.cells / (ms * 1e-3) / 1e12}))
+
+
 def copy_probe():
     """A plain device copy of 1 GiB, run under the HBM counters to calibrate
     FETCH_SIZE / WRITE_SIZE."""
@@ -186,6 +212,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--mlp-probe", type=int, default=0, metavar="STEPS")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: the benchmark runs on one GPU "
@@ -194,6 +221,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.mlp_probe:
+        mlp_probe(args.mlp_probe)
         return
 
     import torch
