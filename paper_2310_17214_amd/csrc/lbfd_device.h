@@ -278,6 +278,12 @@ struct StepArgs {
     int* list;            // [N] flagged cell indices in mask order
     int* count;           // [1] number of listed cells
     int P_nx, P_ny;       // grid extents (for the list kernel)
+    // base of every plane, filled per launch: separate kernel arguments keep
+    // each plane's base in scalar registers, so an access costs one shared
+    // 32-bit lane offset instead of a 64-bit vector address per plane
+    R* gpl[19];               // populations, plane i
+    const R* Ycp[MAXS];       // Y_cur, species k
+    R* Ynp[MAXS];             // Y_nxt, species k
 };
 
 template <typename R>

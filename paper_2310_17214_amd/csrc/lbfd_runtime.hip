@@ -373,6 +373,12 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.count = dptr<int>(c, c->L.count);
     a.P_nx = c->grid.nx;
     a.P_ny = c->grid.ny;
+    for (int i = 0; i < 19; ++i) a.gpl[i] = i < c->Q ? a.g + (size_t)i * N : a.g;
+    for (int k = 0; k < MAXS; ++k) {
+        const int kk = k < c->nsm ? k : 0;
+        a.Ycp[k] = a.Y_cur + (size_t)kk * N;
+        a.Ynp[k] = a.Y_nxt + (size_t)kk * N;
+    }
     hipError_t e;
     if ((e = time_mark(c, LBFD_KERNEL_STEP, false)) != hipSuccess)
         return hip_check(c, e, "timing event");
