@@ -46,6 +46,9 @@ def kernel_hash():
 def make_workload(name):
     from paper_2310_17214_amd import workloads as W
 
+    def log(m):
+        print("bench:", m, file=sys.stderr, flush=True)
+
     if name == "sphere_bed":
         return W.bed_one_step(precision="fp32")
     if name == "sphere_bed_fp64":
@@ -54,6 +57,12 @@ def make_workload(name):
         return W.cylinder_channel()
     if name == "sphere_bed_9sp":
         return W.bed_sphere_9sp(precision="fp32")
+    if name == "elongated_bed_slab":
+        # one GPU's share (third of eight 128-cell slabs, with a halo plane
+        # on each side) of the 1024x256x256 elongated bed
+        return W.bed_elongated_9sp(window=(255, 385), log=log)
+    if name == "elongated_bed":
+        return W.bed_elongated_9sp(log=log)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -67,6 +76,48 @@ def traffic_from_profiles(workload_name, bytes_alg):
     if d.get("kernel_hash") != kernel_hash() or d.get("bytes_per_launch_alg") != bytes_alg:
         return None
     return d.get("bytes_per_launch")
+
+
+XGMI_LINK_GBS = 153.0
+
+
+def halo_measure(ctx, stream, reps=50):
+    """Pack and unpack of the halo planes of both x faces of a slab, timed
+    with HIP events on the context's stream: the copies a slab decomposition
+    adds to each step, and the time one xGMI link would take to move the
+    packed bytes."""
+    import torch
+
+    nx = ctx.shape[2]
+    nb = ctx.halo_bytes()
+    elem = 4 if ctx.precision == "fp32" else 8
+    dt = torch.float32 if elem == 4 else torch.float64
+    bufs = [torch.empty(nb // elem, dtype=dt, device="cuda") for _ in range(2)]
+    faces = ((nx - 2, 1, 0, 1), (1, -1, nx - 1, -1))  # (pack x, dir, unpack x, dir)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for _ in range(3):
+        for (xp, d, _, _), b in zip(faces, bufs):
+            ctx.halo_pack(xp, d, b)
+    ev[0].record(stream)
+    for _ in range(reps):
+        for (xp, d, _, _), b in zip(faces, bufs):
+            ctx.halo_pack(xp, d, b)
+    ev[1].record(stream)
+    for _ in range(reps):
+        for (_, _, xu, d), b in zip(faces, bufs):
+            ctx.halo_unpack(xu, d, b)
+    ev[2].record(stream)
+    ctx.synchronize()
+    pack_us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    unpack_us = ev[1].elapsed_time(ev[2]) * 1e3 / reps
+    moved = 2 * 2 * nb  # both faces, read + write
+    return {"bytes_per_face": nb, "planes_per_face": nb // (elem * ctx.shape[0] * ctx.shape[1]),
+            "pack_both_faces_us": round(pack_us, 2),
+            "unpack_both_faces_us": round(unpack_us, 2),
+            "pack_GBps": round(moved / (pack_us * 1e-6) / 1e9, 1),
+            "unpack_GBps": round(moved / (unpack_us * 1e-6) / 1e9, 1),
+            "xgmi_one_link_us_per_face": round(nb / (XGMI_LINK_GBS * 1e9) * 1e6, 2),
+            "note": "halo copies only; the transfers between GPUs are not run"}
 
 
 def cpu_baseline(wl, target_s=15.0):
@@ -230,6 +281,7 @@ def main():
 
     from paper_2310_17214_amd import lbfd
 
+    print(f"bench: building workload {args.workload}", file=sys.stderr, flush=True)
     wl = make_workload(args.workload)
     print(f"bench: {wl.name}, {wl.cells} cells, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
@@ -293,7 +345,11 @@ def main():
                         "n_nonfinite": diag["n_nonfinite"]},
         "wall_s": round(wall, 3),
     }
-    if not args.no_surrogate:
+    if wl.name.startswith("elongated_bed") and "_slab_" in wl.name:
+        print("bench: halo planes", file=sys.stderr, flush=True)
+        out["halo"] = halo_measure(ctx, stream)
+        out["halo"]["step_ms"] = round(ms_step, 4)
+    if not args.no_surrogate and args.workload == "sphere_bed":
         print("bench: surrogate vs exact chemistry (9-species bed)", file=sys.stderr, flush=True)
         out["surrogate"] = surrogate_measure(
             log=lambda m: print("bench:", m, file=sys.stderr, flush=True))

@@ -114,8 +114,10 @@ typedef struct {
     const double* M;          /* [ns] molar masses                                */
     const double* dhf;        /* [ns] formation enthalpy per unit mass [cp*K]     */
     const double* mu_star;    /* [ns] species viscosity / reference viscosity     */
-    const int32_t* nu_f;      /* [nr][ns] reactant stoichiometric coefficients    */
-    const int32_t* nu_r;      /* [nr][ns] product stoichiometric coefficients     */
+    const int32_t* nu_f;      /* [nr][ns] reactant stoichiometric coefficients,
+                                 0..3, summing to at most 4 per reaction         */
+    const int32_t* nu_r;      /* [nr][ns] product stoichiometric coefficients,
+                                 0..3, summing to at most 4 per reaction         */
     const double* A;          /* [nr] k_f = A T^beta exp(-theta/T)                */
     const double* beta;       /* [nr]                                             */
     const double* theta;      /* [nr] activation temperature [K]                  */
@@ -288,6 +290,24 @@ lbfd_status lbfd_trainer_gradient(lbfd_trainer* tr, const float* x, const float*
 lbfd_status lbfd_trainer_export(lbfd_trainer* tr, float* weights, float* norm, float* envelope);
 lbfd_status lbfd_trainer_destroy(lbfd_trainer* tr);
 const char* lbfd_trainer_last_error(const lbfd_trainer* tr);
+
+/* ------------------------------------------------------------------------
+ * Halo planes: the strided copies that a decomposition of the grid into slabs
+ * along x exchanges between neighbouring GPUs each step (the one-cell
+ * stencils of the LB streaming, Sec. 2.2, and of the FD transport, Eqs. 5
+ * and 6, reach one plane across a slab face).  For the plane x (0 <= x < nx)
+ * and the direction dir (-1 or +1), the buffer holds, plane after plane and
+ * [z][y] within a plane, the population slots as stored of the directions
+ * with c_x = dir (5 in D3Q19, 3 in D2Q9), then T and Y_1..Y_ns of the
+ * current state, in the device precision: lbfd_halo_bytes bytes.  Pack
+ * copies the plane into the buffer, unpack copies a buffer into the plane.
+ * A rightward exchange packs (nx - 2, +1) on one slab and unpacks it at
+ * (0, +1) on its right neighbour.  dev_buf: caller-owned device memory;
+ * enqueued on the context's stream; LBFD_E_INVAL for x or dir out of range.
+ * ------------------------------------------------------------------------ */
+lbfd_status lbfd_halo_bytes(const lbfd_ctx* ctx, size_t* bytes);
+lbfd_status lbfd_halo_pack(lbfd_ctx* ctx, int32_t x, int32_t dir, void* dev_buf);
+lbfd_status lbfd_halo_unpack(lbfd_ctx* ctx, int32_t x, int32_t dir, const void* dev_buf);
 
 /* Per-kernel launch timing (measurement hook).  While enabled, every launch
  * of the fused step kernel, of the FP64 reaction-island kernel and of the

@@ -25,6 +25,18 @@ enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INLET = 2, BC_OUTLET = 3 };
 enum { FD_PERIODIC = 0, FD_DIRICHLET = 1, FD_NEUMANN = 2 };
 enum { PH_LB = 1, PH_FD = 2, PH_CHEM = 4 };
 
+// One reaction: Arrhenius data, the species of each side's concentration
+// product as four 8-bit indices (ascending; a species of order 2 appears
+// twice; unused slots hold the species bound, whose concentration slot is 1),
+// and the net stoichiometric coefficients nu'' - nu' as numbers.
+template <typename R>
+struct Rxn {
+    R A, beta, theta, lnKc_a, lnKc_b;
+    uint32_t fidx, ridx;
+    int32_t rev;
+    R nud[MAXS];
+};
+
 // Every constant the kernels read, in the kernel's arithmetic type.  Lives in
 // the device workspace and is read with wave-uniform (scalar) loads.
 template <typename R>
@@ -40,9 +52,7 @@ struct Par {
     R rD_fac[MAXS];   // 1/(cp Le_k)
     R M[MAXS], invM[MAXS], dhf[MAXS], mu_star[MAXS];
     R Phi[MAXS][MAXS];
-    R A[MAXR], beta[MAXR], theta[MAXR], lnKc_a[MAXR], lnKc_b[MAXR];
-    int rev[MAXR];
-    int8_t nu_f[MAXR][MAXS], nu_r[MAXR][MAXS], nu_d[MAXR][MAXS];
+    Rxn<R> rx[MAXR];
 };
 
 // ------------------------------------------------------------------ lattice
@@ -155,45 +165,51 @@ __device__ __forceinline__ R eq_e(R cu, R uu) {
 }
 
 // ---------------------------------------------------------------- chemistry
+// Load of a wave-uniform table entry through the constant address space, so
+// that it becomes a scalar load even after the kernel has stored to memory.
+template <typename T>
+__device__ __forceinline__ T ldc(const T& v) {
+    return *(const __attribute__((address_space(4))) T*)(uintptr_t)&v;
+}
+
+// The parameter block as the kernels see it: a generic reference whose
+// pointer comes from the constant address space, so that every uniform read
+// of it compiles to a scalar load (the block does not change during a launch).
+template <typename T>
+__device__ __forceinline__ const T& const_block(const T* p) {
+    return *(const T*)(const __attribute__((address_space(4))) T*)(uintptr_t)p;
+}
+
 // Mass-action Arrhenius production rates (omega_k = M_k sum_j s_kj Q_j,
-// omega_T = -sum_k dh_k omega_k), evaluated in type C.
+// omega_T = -sum_k dh_k omega_k), evaluated in type C.  The concentration
+// products index the concentrations with the reaction's (uniform) species
+// indices, which indexes registers directly; each factor multiplies in
+// ascending species order, as the definition's product is written.
 template <typename C, int NSM>
 __device__ __forceinline__ void rates(const Par<C>& P, C T, const C* Y, C rho, C* wk, C& wT) {
-    C X[LBFD_NA(NSM)];
+    C X[NSM + 1];
 #pragma unroll
     for (int k = 0; k < NSM; ++k) {
         X[k] = rho * Y[k] * P.invM[k];
         wk[k] = C(0);
     }
+    X[NSM] = C(1);
     const C invT = rcp(T);
     const C lnT = P.any_beta ? flog(T) : C(0);
-    for (int j = 0; j < P.nr; ++j) {
-        C kf = P.A[j] * fexp(P.beta[j] * lnT - P.theta[j] * invT);
-        C qf = kf;
-#pragma unroll
-        for (int k = 0; k < NSM; ++k) {
-            int e = P.nu_f[j][k];
-            if (e > 0) qf *= X[k];
-            if (e > 1) qf *= X[k];
-            if (e > 2) qf *= X[k];
-        }
-        C Qj = qf;
-        if (P.rev[j]) {
-            C qr = kf * fexp(-(P.lnKc_a[j] + P.lnKc_b[j] * invT));
-#pragma unroll
-            for (int k = 0; k < NSM; ++k) {
-                int e = P.nu_r[j][k];
-                if (e > 0) qr *= X[k];
-                if (e > 1) qr *= X[k];
-                if (e > 2) qr *= X[k];
-            }
+    const int nr = ldc(P.nr);
+    for (int j = 0; j < nr; ++j) {
+        const Rxn<C>& r = P.rx[j];
+        const C kf = ldc(r.A) * fexp(ldc(r.beta) * lnT - ldc(r.theta) * invT);
+        const uint32_t f = ldc(r.fidx);
+        C Qj = kf * X[f & 255u] * X[(f >> 8) & 255u] * X[(f >> 16) & 255u] * X[f >> 24];
+        if (ldc(r.rev)) {
+            const uint32_t b = ldc(r.ridx);
+            const C qr = kf * fexp(-(ldc(r.lnKc_a) + ldc(r.lnKc_b) * invT)) * X[b & 255u] *
+                         X[(b >> 8) & 255u] * X[(b >> 16) & 255u] * X[b >> 24];
             Qj -= qr;
         }
 #pragma unroll
-        for (int k = 0; k < NSM; ++k) {
-            int d = P.nu_d[j][k];
-            if (d != 0) wk[k] += C(d) * Qj;
-        }
+        for (int k = 0; k < NSM; ++k) wk[k] += ldc(r.nud[k]) * Qj;
     }
     C w = C(0);
 #pragma unroll
@@ -284,6 +300,18 @@ struct StepArgs {
     R* gpl[19];               // populations, plane i
     const R* Ycp[MAXS];       // Y_cur, species k
     R* Ynp[MAXS];             // Y_nxt, species k
+};
+
+// Halo planes of one x face (the strided copies a slab decomposition along x
+// exchanges): plane p of the list, cells (x_face, y, z) <-> buf[p][z][y].
+constexpr int HALO_MAX_PLANES = 24;
+static_assert(HALO_MAX_PLANES >= 5 + 1 + MAXS, "halo plane table");
+template <typename R>
+struct HaloArgs {
+    R* plane[HALO_MAX_PLANES];
+    int nplanes, nx, ny, nz, x;
+    R* buf;
+    int pack;  // 1: planes -> buf, 0: buf -> planes
 };
 
 template <typename R>

@@ -77,4 +77,7 @@ hipError_t launch_sample_f32(int nsm, const float* T, const float* Y, int N, con
     default: return hipErrorInvalidValue;
     }
 }
+hipError_t launch_halo_f32(const HaloArgs<float>& a, hipStream_t s) {
+    return launch_halo_t<float>(a, s);
+}
 }  // namespace lbfd

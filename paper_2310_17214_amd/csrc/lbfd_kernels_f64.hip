@@ -38,4 +38,7 @@ int step_tile_h_f64(int dim, int nsm) {
     default: return tile_h_t<double, 16>(dim);
     }
 }
+hipError_t launch_halo_f64(const HaloArgs<double>& a, hipStream_t s) {
+    return launch_halo_t<double>(a, s);
+}
 }  // namespace lbfd

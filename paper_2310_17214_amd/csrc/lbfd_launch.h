@@ -24,6 +24,9 @@ hipError_t launch_mlp_eval_f32(int nsm, const float* T, const float* Y, int n, f
 hipError_t launch_sample_f32(int nsm, const float* T, const float* Y, int N, const int* cells,
                              int n, float* x, float* y, const Par<double>* PD, float p_in,
                              hipStream_t s);
+// halo planes of an x face
+hipError_t launch_halo_f32(const HaloArgs<float>& a, hipStream_t s);
+hipError_t launch_halo_f64(const HaloArgs<double>& a, hipStream_t s);
 // cell rows per workgroup tile of the step kernel (tiles are 64 cells wide)
 int step_tile_h_f32(int dim, int nsm);
 int step_tile_h_f64(int dim, int nsm);

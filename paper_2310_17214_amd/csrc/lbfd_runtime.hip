@@ -222,19 +222,28 @@ Par<R> build_par(const lbfd_ctx* c) {
         for (int j = 0; j < c->ns; ++j)
             P.Phi[k][j] =
                 (R)wilke(c->mech.mu_star[k], c->mech.mu_star[j], c->mech.M[k], c->mech.M[j]);
+    // the index words pad with the kernel's species bound (its slot of 1)
+    const uint32_t pad = (uint32_t)nsm_bucket(c->ns);
     for (int j = 0; j < P.nr; ++j) {
-        P.A[j] = (R)c->mech.A[j];
-        P.beta[j] = (R)c->mech.beta[j];
-        P.theta[j] = (R)c->mech.theta[j];
-        P.lnKc_a[j] = (R)c->mech.lnKc_a[j];
-        P.lnKc_b[j] = (R)c->mech.lnKc_b[j];
-        P.rev[j] = c->mech.rev[j];
+        Rxn<R>& x = P.rx[j];
+        x.A = (R)c->mech.A[j];
+        x.beta = (R)c->mech.beta[j];
+        x.theta = (R)c->mech.theta[j];
+        x.lnKc_a = (R)c->mech.lnKc_a[j];
+        x.lnKc_b = (R)c->mech.lnKc_b[j];
+        x.rev = c->mech.rev[j];
+        uint32_t fw = 0, rw = 0;
+        int nf = 0, nr = 0;
         for (int k = 0; k < c->ns; ++k) {
             const int f = c->mech.nu_f[j * c->ns + k], r = c->mech.nu_r[j * c->ns + k];
-            P.nu_f[j][k] = (int8_t)f;
-            P.nu_r[j][k] = (int8_t)r;
-            P.nu_d[j][k] = (int8_t)(r - f);
+            for (int e = 0; e < f; ++e) fw |= (uint32_t)k << (8 * nf++);
+            for (int e = 0; e < r; ++e) rw |= (uint32_t)k << (8 * nr++);
+            x.nud[k] = (R)(r - f);
         }
+        for (; nf < 4; ++nf) fw |= pad << (8 * nf);
+        for (; nr < 4; ++nr) rw |= pad << (8 * nr);
+        x.fidx = fw;
+        x.ridx = rw;
     }
     return P;
 }
@@ -542,13 +551,18 @@ lbfd_status lbfd_set_mechanism(lbfd_ctx* c, const lbfd_mechanism* m) {
         h.lnKc_a.push_back(m->lnKc_a[j]);
         h.lnKc_b.push_back(m->lnKc_b[j]);
         h.rev.push_back(m->reversible[j] ? 1 : 0);
+        int order_f = 0, order_r = 0;
         for (int k = 0; k < ns; ++k) {
             const int f = m->nu_f[j * ns + k], r = m->nu_r[j * ns + k];
             if (f < 0 || f > 3 || r < 0 || r > 3)
                 return fail(c, LBFD_E_INVAL, "stoichiometric coefficients must be 0..3");
             h.nu_f.push_back(f);
             h.nu_r.push_back(r);
+            order_f += f;
+            order_r += r;
         }
+        if (order_f > 4 || order_r > 4)
+            return fail(c, LBFD_E_INVAL, "reaction order of a side above 4");
     }
     lbfd_status st = set_device(c);
     if (st) return st;
@@ -923,6 +937,68 @@ lbfd_status lbfd_sample_states(lbfd_ctx* c, const int32_t* cells, int32_t n, flo
     return hip_check(c, launch_sample_f32(c->nsm, T, Y, (int)c->N, cells, n, x, y,
                                           dptr<Par<double>>(c, c->L.pard), 1.f, c->stream),
                      "sample launch");
+}
+
+// ---------------------------------------------------------- halo planes
+extern "C++" {
+namespace {
+template <typename R>
+int halo_planes(lbfd_ctx* c, int dir, R** out) {
+    const size_t N = c->N;
+    R* g = dptr<R>(c, c->L.g);
+    const int* cx = c->dim == 2 ? Lat<2>::cx : Lat<3>::cx;
+    int n = 0;
+    for (int i = 0; i < c->Q; ++i)
+        if (cx[i] == dir) out[n++] = g + (size_t)i * N;
+    out[n++] = dptr<R>(c, c->cur ? c->L.T1 : c->L.T0);
+    R* Y = dptr<R>(c, c->cur ? c->L.Y1 : c->L.Y0);
+    for (int k = 0; k < c->ns; ++k) out[n++] = Y + (size_t)k * N;
+    return n;
+}
+template <typename R>
+lbfd_status halo_copy(lbfd_ctx* c, int x, int dir, void* buf, int pack) {
+    HaloArgs<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.nplanes = halo_planes<R>(c, dir, a.plane);
+    a.nx = c->grid.nx;
+    a.ny = c->grid.ny;
+    a.nz = c->grid.nz;
+    a.x = x;
+    a.buf = reinterpret_cast<R*>(buf);
+    a.pack = pack;
+    hipError_t e;
+    if constexpr (sizeof(R) == 4)
+        e = launch_halo_f32(a, c->stream);
+    else
+        e = launch_halo_f64(a, c->stream);
+    return hip_check(c, e, "halo launch");
+}
+lbfd_status halo_entry(lbfd_ctx* c, int32_t x, int32_t dir, const void* buf, int pack) {
+    if (!c || !buf) return LBFD_E_INVAL;
+    if (x < 0 || x >= c->grid.nx) return fail(c, LBFD_E_INVAL, "halo plane outside the grid");
+    if (dir != -1 && dir != 1) return fail(c, LBFD_E_INVAL, "halo direction must be -1 or +1");
+    if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    void* b = const_cast<void*>(buf);
+    return c->fp32 ? halo_copy<float>(c, x, dir, b, pack) : halo_copy<double>(c, x, dir, b, pack);
+}
+}  // namespace
+}  // extern "C++"
+
+lbfd_status lbfd_halo_bytes(const lbfd_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return LBFD_E_INVAL;
+    const int nout = c->dim == 2 ? 3 : 5;
+    *bytes = (size_t)(nout + 1 + c->ns) * c->grid.ny * c->grid.nz * elem(c);
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_halo_pack(lbfd_ctx* c, int32_t x, int32_t dir, void* buf) {
+    return halo_entry(c, x, dir, buf, 1);
+}
+
+lbfd_status lbfd_halo_unpack(lbfd_ctx* c, int32_t x, int32_t dir, const void* buf) {
+    return halo_entry(c, x, dir, buf, 0);
 }
 
 lbfd_status lbfd_set_timing(lbfd_ctx* c, int32_t enable) {

@@ -30,6 +30,7 @@ EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd
             "lbfd_step_phase", "lbfd_read", "lbfd_diagnostics", "lbfd_synchronize",
             "lbfd_step_bytes_per_cell", "lbfd_set_timing", "lbfd_kernel_time",
             "lbfd_set_surrogate", "lbfd_surrogate_eval", "lbfd_sample_states",
+            "lbfd_halo_bytes", "lbfd_halo_pack", "lbfd_halo_unpack",
             "lbfd_trainer_workspace_bytes", "lbfd_trainer_create", "lbfd_trainer_fit_norm",
             "lbfd_trainer_set_weights", "lbfd_trainer_step", "lbfd_trainer_gradient",
             "lbfd_trainer_export", "lbfd_trainer_destroy", "lbfd_trainer_last_error",
@@ -107,6 +108,9 @@ def lib():
         L.lbfd_set_surrogate.argtypes = [vp, _fp, _fp, _fp]
         L.lbfd_surrogate_eval.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp]
         L.lbfd_sample_states.argtypes = [vp, vp, C.c_int32, vp, vp]
+        L.lbfd_halo_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+        L.lbfd_halo_pack.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.lbfd_halo_unpack.argtypes = [vp, C.c_int32, C.c_int32, vp]
         L.lbfd_trainer_workspace_bytes.argtypes = [C.POINTER(TrainCfg), C.POINTER(C.c_size_t)]
         L.lbfd_trainer_create.argtypes = [C.POINTER(TrainCfg), vp, C.c_size_t, vp, C.POINTER(vp)]
         L.lbfd_trainer_fit_norm.argtypes = [vp, vp, vp, C.c_int32]
@@ -207,6 +211,7 @@ class Context:
         self.Q = 9 if self.dim == 2 else 19
         self.shape = (setup["nz"], setup["ny"], setup["nx"])
         self.N = int(np.prod(self.shape))
+        self.precision = "fp32" if setup.get("precision", "fp64") == "fp32" else "fp64"
         self._grid = make_grid(setup)
         nbytes = C.c_size_t()
         self._check(L.lbfd_workspace_bytes(C.byref(self._grid), C.byref(nbytes)), None)
@@ -338,6 +343,27 @@ class Context:
         self._check(lib().lbfd_sample_states(self._h, cells.data_ptr(), n, x.data_ptr(),
                                              y.data_ptr()))
         return x, y
+
+    # ---------------------------------------------------- halo planes
+    def halo_bytes(self):
+        n = C.c_size_t()
+        self._check(lib().lbfd_halo_bytes(self._h, C.byref(n)))
+        return n.value
+
+    def _halo_buf(self, buf):
+        if not buf.is_cuda or not buf.is_contiguous():
+            raise ValueError("halo buffer must be a contiguous CUDA tensor")
+        if buf.numel() * buf.element_size() < self.halo_bytes():
+            raise ValueError("halo buffer too small")
+        return buf.data_ptr()
+
+    def halo_pack(self, x, direction, buf):
+        """Pack plane x, populations with c_x = direction, then T and Y_k."""
+        self._check(lib().lbfd_halo_pack(self._h, int(x), int(direction), self._halo_buf(buf)))
+
+    def halo_unpack(self, x, direction, buf):
+        self._check(lib().lbfd_halo_unpack(self._h, int(x), int(direction),
+                                           self._halo_buf(buf)))
 
     def set_timing(self, enable=True):
         self._check(lib().lbfd_set_timing(self._h, int(bool(enable))))

@@ -573,6 +573,51 @@ def bed_sphere_9sp(nx=256, ny=128, nz=128, precision="fp32", seed=2, bed=(32, 22
     return wl
 
 
+def bed_elongated_9sp(nx=1024, ny=256, nz=256, precision="fp32", seed=5, bed=(64, 960),
+                      x_split=352, porosity=0.40, sphere_share=0.5, steps=20000, window=None,
+                      mech_seed=33, T_burnt=1100.0, log=None) -> Workload:
+    """3-D D3Q19 elongated bed (default 1024x256x256) of seeded particles, half
+    spheres and half superquadrics (r_eq = 8, porosity 0.4), with the
+    9-species mechanism and the mixture transport of bed_superquadric_9sp.
+
+    window=(x0, x1) builds only the cells x0 <= x < x1 of that bed: the share
+    of one GPU in a decomposition into slabs along x, with one halo plane on
+    each side (e.g. (255, 385) for the third of eight 128-cell slabs).  Its
+    x faces keep the inlet and outlet rules; in a decomposed run the halo
+    exchange overwrites them."""
+    mech = mech_synthetic9(seed=mech_seed)
+    rng = np.random.default_rng(seed + 77)
+    Le = rng.uniform(0.8, 1.2, 9).tolist()
+    Le[8] = 1.0
+    x0, x1 = (0, nx) if window is None else window
+    if not 0 <= x0 < x1 <= nx:
+        raise ValueError("window outside the bed")
+    wx = x1 - x0
+    s = _reactive_bed_setup(3, wx, ny, nz, mech, SYNTH9_Y_IN, precision, T_s=700.0,
+                            nu_in=0.006, u_in=0.005, transport=1, Le=Le,
+                            n_sub=int(mech["n_sub"]))
+    parts = superquadric_bed((nz, ny, nx), bed, 8.0, porosity, seed, sphere_share=sphere_share)
+    if log:
+        log(f"placed {len(parts)} particles")
+    if window is not None:
+        reach = 8.0 * 1.6 + 2.0 * s["eta"] + 2.0
+        parts = [dataclasses.replace(p, centre=p.centre - np.array([x0, 0.0, 0.0]))
+                 for p in parts if x0 - reach <= p.centre[0] < x1 + reach]
+    shape = (nz, ny, wx)
+    phi = bed_phi(shape, parts, s["eta"], (False, True, True))
+    if log:
+        log("phase field done")
+    T0, Y0 = _split_init(shape, phi, x_split - x0, T_IN, SYNTH9_Y_IN, T_burnt, burnt_synth9(),
+                         s["T_s"])
+    name = f"elongated_bed_9species_d3q19_{nx}x{ny}x{nz}"
+    if window is not None:
+        name += f"_slab_x{x0}-{x1}"
+    wl = Workload(name, s, phi, T0, Y0, None, steps)
+    wl.particles = parts
+    wl.bed = (bed[0] - x0, bed[1] - x0)
+    return wl
+
+
 # ----------------------------------------------------- small test setups
 
 def periodic_box(dim, n, ns=0, precision="fp64"):

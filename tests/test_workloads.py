@@ -80,3 +80,20 @@ def test_cfg1_parameters():
     assert abs(s["u_in"][0] * 20.0 / s["nu_in"] - 20.0) < 1e-12   # Re = 20 on D = 20
     assert abs(s["T_s"] - 450.0) < 1e-12
     assert wl.phi[0, 32, 32] > 0.99 and wl.phi[0, 5, 100] < 1e-6
+
+
+def test_slab_window_is_a_slice_of_the_whole_bed():
+    """A window of the elongated bed (one GPU's share in a slab decomposition)
+    holds exactly the phase field, temperature and composition of those
+    cells of the whole bed."""
+    kw = dict(nx=96, ny=16, nz=16, bed=(8, 88), x_split=40, steps=0)
+    full = W.bed_elongated_9sp(**kw)
+    part = W.bed_elongated_9sp(window=(30, 58), **kw)
+    assert part.phi.shape == (16, 16, 28) and part.setup["nx"] == 28
+    assert np.array_equal(part.phi, full.phi[:, :, 30:58])
+    assert np.array_equal(part.T0, full.T0[:, :, 30:58])
+    assert np.array_equal(part.Y0, full.Y0[:, :, :, 30:58])
+    kinds = {p.kind for p in full.particles}
+    assert kinds == {"sphere", "superquadric"}
+    solid = W.sharp_solid(full.phi.shape, full.particles, (False, True, True))
+    assert abs(W.bed_porosity(solid, full.bed) - 0.40) < 0.06
