@@ -25,16 +25,19 @@ enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INLET = 2, BC_OUTLET = 3 };
 enum { FD_PERIODIC = 0, FD_DIRICHLET = 1, FD_NEUMANN = 2 };
 enum { PH_LB = 1, PH_FD = 2, PH_CHEM = 4 };
 
-// One reaction: Arrhenius data, the species of each side's concentration
-// product as four 8-bit indices (ascending; a species of order 2 appears
-// twice; unused slots hold the species bound, whose concentration slot is 1),
-// and the net stoichiometric coefficients nu'' - nu' as numbers.
+// The reactions, one array per field (so that the data of consecutive
+// reactions are adjacent and load together): Arrhenius data; revf = 1 for a
+// reversible reaction, else 0 (with lnKc = 0, keeping the unused reverse term
+// finite); the species of each side's concentration product as four 8-bit
+// indices (ascending; a species of order 2 appears twice; unused slots hold
+// the species bound, whose concentration slot is 1); the net stoichiometric
+// coefficients nu'' - nu' as numbers.  Entries past nr are inert (A = 0).
 template <typename R>
 struct Rxn {
-    R A, beta, theta, lnKc_a, lnKc_b;
-    uint32_t fidx, ridx;
-    int32_t rev;
-    R nud[MAXS];
+    R A[MAXR], beta[MAXR], theta[MAXR], lnKc_a[MAXR], lnKc_b[MAXR], revf[MAXR];
+    uint32_t fidx[MAXR], ridx[MAXR];
+    int32_t rev[MAXR];
+    R nud[MAXR][MAXS];
 };
 
 // Every constant the kernels read, in the kernel's arithmetic type.  Lives in
@@ -52,7 +55,7 @@ struct Par {
     R rD_fac[MAXS];   // 1/(cp Le_k)
     R M[MAXS], invM[MAXS], dhf[MAXS], mu_star[MAXS];
     R Phi[MAXS][MAXS];
-    Rxn<R> rx[MAXR];
+    Rxn<R> rx;
 };
 
 // ------------------------------------------------------------------ lattice
@@ -165,13 +168,6 @@ __device__ __forceinline__ R eq_e(R cu, R uu) {
 }
 
 // ---------------------------------------------------------------- chemistry
-// Load of a wave-uniform table entry through the constant address space, so
-// that it becomes a scalar load even after the kernel has stored to memory.
-template <typename T>
-__device__ __forceinline__ T ldc(const T& v) {
-    return *(const __attribute__((address_space(4))) T*)(uintptr_t)&v;
-}
-
 // The parameter block as the kernels see it: a generic reference whose
 // pointer comes from the constant address space, so that every uniform read
 // of it compiles to a scalar load (the block does not change during a launch).
@@ -184,7 +180,9 @@ __device__ __forceinline__ const T& const_block(const T* p) {
 // omega_T = -sum_k dh_k omega_k), evaluated in type C.  The concentration
 // products index the concentrations with the reaction's (uniform) species
 // indices, which indexes registers directly; each factor multiplies in
-// ascending species order, as the definition's product is written.
+// ascending species order, as the definition's product is written.  With
+// nine or more species the reactions go in pairs, without a branch on
+// reversibility, so that two reactions' table loads and exponentials overlap.
 template <typename C, int NSM>
 __device__ __forceinline__ void rates(const Par<C>& P, C T, const C* Y, C rho, C* wk, C& wT) {
     C X[NSM + 1];
@@ -196,20 +194,25 @@ __device__ __forceinline__ void rates(const Par<C>& P, C T, const C* Y, C rho, C
     X[NSM] = C(1);
     const C invT = rcp(T);
     const C lnT = P.any_beta ? flog(T) : C(0);
-    const int nr = ldc(P.nr);
-    for (int j = 0; j < nr; ++j) {
-        const Rxn<C>& r = P.rx[j];
-        const C kf = ldc(r.A) * fexp(ldc(r.beta) * lnT - ldc(r.theta) * invT);
-        const uint32_t f = ldc(r.fidx);
-        C Qj = kf * X[f & 255u] * X[(f >> 8) & 255u] * X[(f >> 16) & 255u] * X[f >> 24];
-        if (ldc(r.rev)) {
-            const uint32_t b = ldc(r.ridx);
-            const C qr = kf * fexp(-(ldc(r.lnKc_a) + ldc(r.lnKc_b) * invT)) * X[b & 255u] *
-                         X[(b >> 8) & 255u] * X[(b >> 16) & 255u] * X[b >> 24];
-            Qj -= qr;
-        }
+    constexpr int G = NSM >= 9 ? 2 : 1;
+    const Rxn<C>& r = P.rx;
+    const int ng = (P.nr + G - 1) / G;
+    for (int g = 0; g < ng; ++g) {
 #pragma unroll
-        for (int k = 0; k < NSM; ++k) wk[k] += ldc(r.nud[k]) * Qj;
+        for (int u = 0; u < G; ++u) {
+            const int j = g * G + u;
+            const C kf = r.A[j] * fexp(r.beta[j] * lnT - r.theta[j] * invT);
+            const uint32_t f = r.fidx[j];
+            C Qj = kf * X[f & 255u] * X[(f >> 8) & 255u] * X[(f >> 16) & 255u] * X[f >> 24];
+            if (G > 1 || r.rev[j]) {
+                const uint32_t b = r.ridx[j];
+                const C qr = kf * fexp(-(r.lnKc_a[j] + r.lnKc_b[j] * invT)) * X[b & 255u] *
+                             X[(b >> 8) & 255u] * X[(b >> 16) & 255u] * X[b >> 24];
+                Qj -= r.revf[j] * qr;
+            }
+#pragma unroll
+            for (int k = 0; k < NSM; ++k) wk[k] += r.nud[j][k] * Qj;
+        }
     }
     C w = C(0);
 #pragma unroll

@@ -224,26 +224,30 @@ Par<R> build_par(const lbfd_ctx* c) {
                 (R)wilke(c->mech.mu_star[k], c->mech.mu_star[j], c->mech.M[k], c->mech.M[j]);
     // the index words pad with the kernel's species bound (its slot of 1)
     const uint32_t pad = (uint32_t)nsm_bucket(c->ns);
+    Rxn<R>& x = P.rx;
+    for (int j = 0; j < MAXR; ++j) x.fidx[j] = x.ridx[j] = pad * 0x01010101u;
     for (int j = 0; j < P.nr; ++j) {
-        Rxn<R>& x = P.rx[j];
-        x.A = (R)c->mech.A[j];
-        x.beta = (R)c->mech.beta[j];
-        x.theta = (R)c->mech.theta[j];
-        x.lnKc_a = (R)c->mech.lnKc_a[j];
-        x.lnKc_b = (R)c->mech.lnKc_b[j];
-        x.rev = c->mech.rev[j];
+        x.A[j] = (R)c->mech.A[j];
+        x.beta[j] = (R)c->mech.beta[j];
+        x.theta[j] = (R)c->mech.theta[j];
+        x.rev[j] = c->mech.rev[j];
+        x.revf[j] = (R)x.rev[j];
+        if (x.rev[j]) {
+            x.lnKc_a[j] = (R)c->mech.lnKc_a[j];
+            x.lnKc_b[j] = (R)c->mech.lnKc_b[j];
+        }
         uint32_t fw = 0, rw = 0;
         int nf = 0, nr = 0;
         for (int k = 0; k < c->ns; ++k) {
             const int f = c->mech.nu_f[j * c->ns + k], r = c->mech.nu_r[j * c->ns + k];
             for (int e = 0; e < f; ++e) fw |= (uint32_t)k << (8 * nf++);
             for (int e = 0; e < r; ++e) rw |= (uint32_t)k << (8 * nr++);
-            x.nud[k] = (R)(r - f);
+            x.nud[j][k] = (R)(r - f);
         }
         for (; nf < 4; ++nf) fw |= pad << (8 * nf);
         for (; nr < 4; ++nr) rw |= pad << (8 * nr);
-        x.fidx = fw;
-        x.ridx = rw;
+        x.fidx[j] = fw;
+        x.ridx[j] = rw;
     }
     return P;
 }

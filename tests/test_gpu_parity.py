@@ -287,3 +287,38 @@ def test_nine_species_crop_fp32_1000_steps():
         if k == "T" or k.startswith("Y"):
             assert e <= 1e-4, (k, e)
     assert ctx.diagnostics()["n_flagged_fp64"] > 0
+
+
+def test_nine_species_mixed_reversibility_and_orders_fp64():
+    """The 9-species crop with every third reaction irreversible, one reaction
+    of order three (2A + B) and one with three product factors, and an even
+    reaction count: the paired, branch-free rate loop against the oracle."""
+    wl = _crop9("fp64")
+    m = wl.setup["mech"]
+    nu_f, nu_r = np.array(m["nu_f"]), np.array(m["nu_r"])
+    nu_f[0][0] = 2
+    nu_r[2][4] = 2
+    keep = 20
+    m2 = dict(m)
+    m2["nu_f"], m2["nu_r"] = nu_f[:keep].tolist(), nu_r[:keep].tolist()
+    for key in ("A", "beta", "theta", "lnKc_a", "lnKc_b"):
+        m2[key] = list(m[key])[:keep]
+    m2["rev"] = [int(j % 3 != 0) for j in range(keep)]
+    wl.setup["mech"] = m2
+    say(f"{wl.name} mixed reversibility, fp64 300 steps")
+    ctx, orc = run_both(wl.setup, wl.phi, wl.T0, wl.Y0, 300)
+    errs = compare(ctx, orc)
+    say(errs)
+    assert max(errs.values()) <= 1e-12, errs
+    assert ctx.diagnostics()["n_flagged_fp64"] == orc.diag()[O.D_FLAGGED] > 0
+
+
+def test_mechanism_order_above_four_is_rejected():
+    wl = _crop9("fp64")
+    m = dict(wl.setup["mech"])
+    nu_f = np.array(m["nu_f"])
+    nu_f[1][0], nu_f[1][1] = 3, 2
+    m["nu_f"] = nu_f.tolist()
+    wl.setup["mech"] = m
+    with pytest.raises(lb().LbfdError):
+        lb().Context(wl.setup, wl.phi)
