@@ -147,21 +147,28 @@ MLP_FLOP_PER_CELL = 2 * (11 * 256 + 256 * 256 + 256 * 9)   # 141,312 (9 species)
 BF16_PEAK_TFLOPS = 2500.0
 
 
-def surrogate_measure(steps=200, seed=4, log=None):
-    """Surrogate against exact chemistry on the 9-species sphere bed
-    (256x128x128): train on pairs sampled from an exact run (every 25th step
-    of 5000, 10,000 cells each, 90/10 split), then time both paths and compare
-    T after 1000 steps from the same initial state."""
+def surrogate_measure(wl=None, steps=200, seed=4, log=None, sample_steps=5000, every=25,
+                      per_snapshot=10000, err_steps=1000, sweep=True):
+    """Surrogate against exact chemistry, by default on the 9-species sphere
+    bed (256x128x128): train on pairs sampled from an exact run (every 25th
+    step of 5000, 10,000 cells each, 90/10 split), then time both paths and
+    compare T after `err_steps` steps from the same initial state."""
     import torch
 
     from paper_2310_17214_amd import lbfd, surrogate as SG, workloads as W
 
     t0 = time.perf_counter()
-    wl = W.bed_sphere_9sp(precision="fp32")
+    if wl is None:
+        wl = W.bed_sphere_9sp(precision="fp32")
     ns = wl.setup["ns"]
-    x, y = SG.sample_run(wl, steps=5000, every=25, per_snapshot=10000, seed=seed)
+    x, y = SG.sample_run(wl, steps=sample_steps, every=every, per_snapshot=per_snapshot,
+                         seed=seed)
     t_sample = time.perf_counter() - t0
+    if log:
+        log(f"sampled {x.shape[0]} pairs in {t_sample:.1f} s")
     (xt, yt), (xh, yh) = SG.split(x, y, 0.1, seed=seed + 1)
+    n_pairs = int(x.shape[0])
+    del x, y
     t1 = time.perf_counter()
     w, nrm, env, losses = SG.train(xt, yt, ns, epochs=6, batch=8192, seed=seed + 2, log=log)
     torch.cuda.synchronize()
@@ -186,11 +193,39 @@ def surrogate_measure(steps=200, seed=4, log=None):
         ctx.step(steps)
         kt = {k: ctx.kernel_time(i) for i, k in enumerate(("step", "island", "mlp"))}
         ctx.set_timing(False)
-        ctx.step(1000 - 20 - 2 * steps)
+        ctx.step(err_steps - 20 - 2 * steps)
         d = ctx.diagnostics()
-        res[mode] = {"ms": ms, "kt": kt, "T": ctx.fields()["T"], "diag": d}
+        res[mode] = {"ms": ms, "kt": kt, "T": ctx.read(lbfd.F_T), "diag": d}
+        del ctx
+        if log:
+            log(f"{mode}: {ms:.3f} ms per step")
     ex, su = res["exact"], res["surrogate"]
     err = float(np.max(np.abs(su["T"] - ex["T"]) / ex["T"]))
+    # cost of the exact path against the number of reaction sub-steps (same
+    # mechanism and state, n_sub overridden): where the surrogate would pay
+    by_nsub = {}
+    for k in ((3, 6, 12, 24) if sweep else ()):
+        s = dict(wl.setup)
+        s["n_sub"] = k
+        ctx = lbfd.Context(s, wl.phi)
+        ctx.init_state(wl.T0, wl.Y0)
+        ctx.step(10)
+        ctx.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.step(50)
+        e1.record(ctx.stream)
+        ctx.synchronize()
+        by_nsub[k] = e0.elapsed_time(e1) / 50
+        del ctx
+    ks = sorted(by_nsub)
+    even = None
+    for a, b in zip(ks, ks[1:]):
+        ya, yb = by_nsub[a], by_nsub[b]
+        if ya <= su["ms"] <= yb:
+            even = a + (b - a) * (su["ms"] - ya) / (yb - ya)
+            break
     mlp_ms = su["kt"]["mlp"][1]
     tflops = MLP_FLOP_PER_CELL * wl.cells / (mlp_ms * 1e-3) / 1e12
     return {
@@ -198,18 +233,20 @@ def surrogate_measure(steps=200, seed=4, log=None):
         "n_sub": int(wl.setup["n_sub"]),
         "exact_ms_per_step": round(ex["ms"], 5), "surrogate_ms_per_step": round(su["ms"], 5),
         "speedup": round(ex["ms"] / su["ms"], 4),
-        "max_rel_T_err_1000_steps": err, "T_err_bar": 0.01,
-        "fallback_share": su["diag"]["n_fallback"] / (1000.0 * wl.cells),
+        f"max_rel_T_err_{err_steps}_steps": err, "T_err_bar": 0.01,
+        "fallback_share": su["diag"]["n_fallback"] / (float(err_steps) * wl.cells),
         "kernels_ms": {"exact": {k: round(v[1], 5) for k, v in ex["kt"].items()},
                        "surrogate": {k: round(v[1], 5) for k, v in su["kt"].items()}},
         "mlp_roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(tflops / BF16_PEAK_TFLOPS, 4),
                          "flop_per_cell": MLP_FLOP_PER_CELL},
-        "training": {"pairs": int(x.shape[0]), "train_pairs": int(xt.shape[0]),
+        "training": {"pairs": n_pairs, "train_pairs": int(xt.shape[0]),
                      "sample_s": round(t_sample, 2), "train_s": round(t_train, 2),
                      "epochs": len(losses), "final_loss": losses[-1]},
         "heldout_rel_rmse": [None if not np.isfinite(v) else round(float(v), 5) for v in rel],
         "heldout_fallback_share": fb_ho,
+        "exact_ms_per_step_by_n_sub": {str(k): round(v, 5) for k, v in by_nsub.items()} or None,
+        "break_even_n_sub": None if even is None else round(even, 2),
     }
 
 
@@ -349,10 +386,17 @@ def main():
         print("bench: halo planes", file=sys.stderr, flush=True)
         out["halo"] = halo_measure(ctx, stream)
         out["halo"]["step_ms"] = round(ms_step, 4)
+    blog = lambda m: print("bench:", m, file=sys.stderr, flush=True)  # noqa: E731
     if not args.no_surrogate and args.workload == "sphere_bed":
         print("bench: surrogate vs exact chemistry (9-species bed)", file=sys.stderr, flush=True)
-        out["surrogate"] = surrogate_measure(
-            log=lambda m: print("bench:", m, file=sys.stderr, flush=True))
+        out["surrogate"] = surrogate_measure(log=blog)
+    elif not args.no_surrogate and args.workload == "elongated_bed":
+        # the elongated bed's own surrogate: pairs from 2000 exact steps of it
+        del ctx
+        print("bench: surrogate vs exact chemistry (elongated bed)", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate_measure(wl, steps=20, log=blog, sample_steps=2000,
+                                             every=25, per_snapshot=25000, err_steps=200,
+                                             sweep=False)
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
