@@ -249,6 +249,37 @@ def test_full_size_bed_one_step_from_gpu_state():
             assert e <= 1e-5, (k, e)
 
 
+@pytest.mark.parametrize("bed", ["sphere_9sp", "superquadric_9sp"])
+def test_full_size_nine_species_bed_one_step_from_gpu_state(bed):
+    """The 9-species beds at full size (256x128x128 spheres, constant Lewis
+    numbers; 384x192x192 superquadrics, Wilke transport and unequal Lewis
+    numbers) in the benchmark's launch configuration: after 20 GPU steps the
+    GPU state is loaded into the oracle and both advance one step."""
+    make = W.bed_sphere_9sp if bed == "sphere_9sp" else W.bed_superquadric_9sp
+    wl = make(precision="fp32", steps=0)
+    wl64 = make(precision="fp64", steps=0)
+    say(f"{wl.name} fp32 full size, 20 + 1 steps")
+    ctx = lb().Context(wl.setup, wl.phi)
+    ctx.init_state(wl.T0, wl.Y0)
+    ctx.step(20)
+    f = ctx.fields()
+    g = ctx.populations()
+    assert np.abs(f["Y"].sum(0) - 1.0).max() <= 2e-6
+    orc = O.Oracle(wl64.setup, wl64.phi)
+    orc.init_state(f["T"], f["Y"])
+    orc.set_populations(g, f["divu"])
+    del g
+    orc.step(1)
+    ctx.step(1)
+    errs = compare(ctx, orc, keys=("T", "Y", "u", "Ph"))
+    say(errs)
+    for k, e in errs.items():
+        if k.startswith("u"):
+            assert e <= 1e-5, (k, e)
+        if k == "T" or k.startswith("Y"):
+            assert e <= 1e-5, (k, e)
+
+
 def _crop9(precision):
     wl = W.bed_superquadric_9sp(nx=37, ny=18, nz=14, precision=precision, bed=(6, 31), x_split=19, steps=0,
                     T_burnt=1400.0)
