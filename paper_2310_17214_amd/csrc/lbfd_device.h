@@ -12,6 +12,7 @@ namespace lbfd {
 
 constexpr int MAXS = 16;
 constexpr int MAXR = 32;
+constexpr int MAXR_TAB = MAXR + 2;  // reaction table entries: two segments, each padded to pairs
 constexpr int BLOCK = 256;       // threads per workgroup: 4 wave64
 constexpr int DIAG_STRIDE = 32;  // doubles of partials per workgroup
 constexpr int FLAG_GROUP = 4 * BLOCK;  // FP64-island mask words per scan group
@@ -31,13 +32,17 @@ enum { PH_LB = 1, PH_FD = 2, PH_CHEM = 4 };
 // finite); the species of each side's concentration product as four 8-bit
 // indices (ascending; a species of order 2 appears twice; unused slots hold
 // the species bound, whose concentration slot is 1); the net stoichiometric
-// coefficients nu'' - nu' as numbers.  Entries past nr are inert (A = 0).
+// coefficients nu'' - nu' as numbers.  Two segments: entries [0, n_lo) are
+// the reactions whose sides have at most two factors (evaluated with two),
+// then [n_lo, n_tab) the others (four), each in the mechanism's order and
+// padded to the kernel's reaction group with inert entries (A = 0).
 template <typename R>
 struct Rxn {
-    R A[MAXR], beta[MAXR], theta[MAXR], lnKc_a[MAXR], lnKc_b[MAXR], revf[MAXR];
-    uint32_t fidx[MAXR], ridx[MAXR];
-    int32_t rev[MAXR];
-    R nud[MAXR][MAXS];
+    R A[MAXR_TAB], beta[MAXR_TAB], theta[MAXR_TAB], lnKc_a[MAXR_TAB], lnKc_b[MAXR_TAB],
+        revf[MAXR_TAB];
+    uint32_t fidx[MAXR_TAB], ridx[MAXR_TAB];
+    int32_t rev[MAXR_TAB];
+    R nud[MAXR_TAB][MAXS];
 };
 
 // Every constant the kernels read, in the kernel's arithmetic type.  Lives in
@@ -45,6 +50,7 @@ struct Rxn {
 template <typename R>
 struct Par {
     int nx, ny, nz, ns, nr;
+    int n_lo, n_tab;  // reaction table segments (see Rxn)
     int n_sub, mu_model, transport, corr, any_beta;
     int lb_bc[6], fd_bc[6];
     R A_u, A_T, inv_eta2, T_s, cp, inv_cp, inv_Pr, rho_in, T_in, mu_ref, S_T_in, S;
@@ -168,6 +174,11 @@ __device__ __forceinline__ R eq_e(R cu, R uu) {
 }
 
 // ---------------------------------------------------------------- chemistry
+template <int V>
+struct Int {
+    static constexpr int value = V;
+};
+
 // The parameter block as the kernels see it: a generic reference whose
 // pointer comes from the constant address space, so that every uniform read
 // of it compiles to a scalar load (the block does not change during a launch).
@@ -196,23 +207,31 @@ __device__ __forceinline__ void rates(const Par<C>& P, C T, const C* Y, C rho, C
     const C lnT = P.any_beta ? flog(T) : C(0);
     constexpr int G = NSM >= 9 ? 2 : 1;
     const Rxn<C>& r = P.rx;
-    const int ng = (P.nr + G - 1) / G;
-    for (int g = 0; g < ng; ++g) {
+    auto react = [&](int j, auto nfac) {
+        constexpr int NF = decltype(nfac)::value;
+        const C kf = r.A[j] * fexp(r.beta[j] * lnT - r.theta[j] * invT);
+        const uint32_t f = r.fidx[j];
+        C Qj = kf;
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
-            const int j = g * G + u;
-            const C kf = r.A[j] * fexp(r.beta[j] * lnT - r.theta[j] * invT);
-            const uint32_t f = r.fidx[j];
-            C Qj = kf * X[f & 255u] * X[(f >> 8) & 255u] * X[(f >> 16) & 255u] * X[f >> 24];
-            if (G > 1 || r.rev[j]) {
-                const uint32_t b = r.ridx[j];
-                const C qr = kf * fexp(-(r.lnKc_a[j] + r.lnKc_b[j] * invT)) * X[b & 255u] *
-                             X[(b >> 8) & 255u] * X[(b >> 16) & 255u] * X[b >> 24];
-                Qj -= r.revf[j] * qr;
-            }
+        for (int q = 0; q < NF; ++q) Qj = Qj * X[(f >> (8 * q)) & 255u];
+        if (G > 1 || r.rev[j]) {
+            const uint32_t b = r.ridx[j];
+            C qr = kf * fexp(-(r.lnKc_a[j] + r.lnKc_b[j] * invT));
 #pragma unroll
-            for (int k = 0; k < NSM; ++k) wk[k] += r.nud[j][k] * Qj;
+            for (int q = 0; q < NF; ++q) qr = qr * X[(b >> (8 * q)) & 255u];
+            Qj -= r.revf[j] * qr;
         }
+#pragma unroll
+        for (int k = 0; k < NSM; ++k) wk[k] += r.nud[j][k] * Qj;
+    };
+    const int n_lo = P.n_lo, n_tab = P.n_tab;
+    for (int j = 0; j < n_lo; j += G) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) react(j + u, Int<2>{});
+    }
+    for (int j = n_lo; j < n_tab; j += G) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) react(j + u, Int<4>{});
     }
     C w = C(0);
 #pragma unroll

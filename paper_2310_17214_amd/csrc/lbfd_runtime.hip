@@ -222,33 +222,51 @@ Par<R> build_par(const lbfd_ctx* c) {
         for (int j = 0; j < c->ns; ++j)
             P.Phi[k][j] =
                 (R)wilke(c->mech.mu_star[k], c->mech.mu_star[j], c->mech.M[k], c->mech.M[j]);
-    // the index words pad with the kernel's species bound (its slot of 1)
-    const uint32_t pad = (uint32_t)nsm_bucket(c->ns);
+    // The reaction table: reactions whose sides have at most two factors
+    // first, then the others, each segment in the mechanism's order and
+    // padded to the kernel's reaction group; index words pad with the
+    // kernel's species bound (its concentration slot holds 1).
+    const int nsm = nsm_bucket(c->ns);
+    const uint32_t pad = (uint32_t)nsm;
+    const int group = nsm >= 9 ? 2 : 1;
     Rxn<R>& x = P.rx;
-    for (int j = 0; j < MAXR; ++j) x.fidx[j] = x.ridx[j] = pad * 0x01010101u;
-    for (int j = 0; j < P.nr; ++j) {
-        x.A[j] = (R)c->mech.A[j];
-        x.beta[j] = (R)c->mech.beta[j];
-        x.theta[j] = (R)c->mech.theta[j];
-        x.rev[j] = c->mech.rev[j];
-        x.revf[j] = (R)x.rev[j];
-        if (x.rev[j]) {
-            x.lnKc_a[j] = (R)c->mech.lnKc_a[j];
-            x.lnKc_b[j] = (R)c->mech.lnKc_b[j];
+    for (int j = 0; j < MAXR_TAB; ++j) x.fidx[j] = x.ridx[j] = pad * 0x01010101u;
+    int e = 0;
+    for (int seg = 0; seg < 2; ++seg) {
+        for (int j = 0; j < P.nr; ++j) {
+            int of = 0, orr = 0;
+            for (int k = 0; k < c->ns; ++k) {
+                of += c->mech.nu_f[j * c->ns + k];
+                orr += c->mech.nu_r[j * c->ns + k];
+            }
+            if ((of <= 2 && orr <= 2) != (seg == 0)) continue;
+            x.A[e] = (R)c->mech.A[j];
+            x.beta[e] = (R)c->mech.beta[j];
+            x.theta[e] = (R)c->mech.theta[j];
+            x.rev[e] = c->mech.rev[j];
+            x.revf[e] = (R)x.rev[e];
+            if (x.rev[e]) {
+                x.lnKc_a[e] = (R)c->mech.lnKc_a[j];
+                x.lnKc_b[e] = (R)c->mech.lnKc_b[j];
+            }
+            uint32_t fw = 0, rw = 0;
+            int nf = 0, nr = 0;
+            for (int k = 0; k < c->ns; ++k) {
+                const int f = c->mech.nu_f[j * c->ns + k], r = c->mech.nu_r[j * c->ns + k];
+                for (int q = 0; q < f; ++q) fw |= (uint32_t)k << (8 * nf++);
+                for (int q = 0; q < r; ++q) rw |= (uint32_t)k << (8 * nr++);
+                x.nud[e][k] = (R)(r - f);
+            }
+            for (; nf < 4; ++nf) fw |= pad << (8 * nf);
+            for (; nr < 4; ++nr) rw |= pad << (8 * nr);
+            x.fidx[e] = fw;
+            x.ridx[e] = rw;
+            ++e;
         }
-        uint32_t fw = 0, rw = 0;
-        int nf = 0, nr = 0;
-        for (int k = 0; k < c->ns; ++k) {
-            const int f = c->mech.nu_f[j * c->ns + k], r = c->mech.nu_r[j * c->ns + k];
-            for (int e = 0; e < f; ++e) fw |= (uint32_t)k << (8 * nf++);
-            for (int e = 0; e < r; ++e) rw |= (uint32_t)k << (8 * nr++);
-            x.nud[j][k] = (R)(r - f);
-        }
-        for (; nf < 4; ++nf) fw |= pad << (8 * nf);
-        for (; nr < 4; ++nr) rw |= pad << (8 * nr);
-        x.fidx[j] = fw;
-        x.ridx[j] = rw;
+        e = (e + group - 1) / group * group;  // inert padding (zeroed, A = 0)
+        if (seg == 0) P.n_lo = e;
     }
+    P.n_tab = e;
     return P;
 }
 
