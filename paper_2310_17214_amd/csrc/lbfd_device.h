@@ -27,9 +27,10 @@ enum { FD_PERIODIC = 0, FD_DIRICHLET = 1, FD_NEUMANN = 2 };
 enum { PH_LB = 1, PH_FD = 2, PH_CHEM = 4 };
 
 // The reactions, one array per field (so that the data of consecutive
-// reactions are adjacent and load together): Arrhenius data; revf = 1 for a
-// reversible reaction, else 0 (with lnKc = 0, keeping the unused reverse term
-// finite); the species of each side's concentration product as four 8-bit
+// reactions are adjacent and load together): Arrhenius data (in the FP32
+// table theta, lnKc_a and lnKc_b are scaled by log2(e), so that the kernels
+// exponentiate in base 2 and beta multiplies log2 T; an irreversible
+// reaction has lnKc_a = +inf, so its reverse term is exactly zero); the species of each side's concentration product as four 8-bit
 // indices (ascending; a species of order 2 appears twice; unused slots hold
 // the species bound, whose concentration slot is 1); the net stoichiometric
 // coefficients nu'' - nu' as numbers.  Two segments: entries [0, n_lo) are
@@ -38,8 +39,7 @@ enum { PH_LB = 1, PH_FD = 2, PH_CHEM = 4 };
 // padded to the kernel's reaction group with inert entries (A = 0).
 template <typename R>
 struct Rxn {
-    R A[MAXR_TAB], beta[MAXR_TAB], theta[MAXR_TAB], lnKc_a[MAXR_TAB], lnKc_b[MAXR_TAB],
-        revf[MAXR_TAB];
+    R A[MAXR_TAB], beta[MAXR_TAB], theta[MAXR_TAB], lnKc_a[MAXR_TAB], lnKc_b[MAXR_TAB];
     uint32_t fidx[MAXR_TAB], ridx[MAXR_TAB];
     int32_t rev[MAXR_TAB];
     R nud[MAXR_TAB][MAXS];
@@ -204,22 +204,36 @@ __device__ __forceinline__ void rates(const Par<C>& P, C T, const C* Y, C rho, C
     }
     X[NSM] = C(1);
     const C invT = rcp(T);
-    const C lnT = P.any_beta ? flog(T) : C(0);
+    // FP32: base-2 exponentials of the base-2 table; FP64: natural ones
+    constexpr bool B2 = sizeof(C) == 4;
+    C lgT = C(0);
+    if (P.any_beta) {
+        if constexpr (B2)
+            lgT = __builtin_amdgcn_logf(T);
+        else
+            lgT = flog(T);
+    }
+    auto ex = [](C v) {
+        if constexpr (B2)
+            return __builtin_amdgcn_exp2f(v);
+        else
+            return fexp(v);
+    };
     constexpr int G = NSM >= 9 ? 2 : 1;
     const Rxn<C>& r = P.rx;
     auto react = [&](int j, auto nfac) {
         constexpr int NF = decltype(nfac)::value;
-        const C kf = r.A[j] * fexp(r.beta[j] * lnT - r.theta[j] * invT);
+        const C kf = r.A[j] * ex(r.beta[j] * lgT - r.theta[j] * invT);
         const uint32_t f = r.fidx[j];
         C Qj = kf;
 #pragma unroll
         for (int q = 0; q < NF; ++q) Qj = Qj * X[(f >> (8 * q)) & 255u];
         if (G > 1 || r.rev[j]) {
             const uint32_t b = r.ridx[j];
-            C qr = kf * fexp(-(r.lnKc_a[j] + r.lnKc_b[j] * invT));
+            C qr = kf * ex(-(r.lnKc_a[j] + r.lnKc_b[j] * invT));
 #pragma unroll
             for (int q = 0; q < NF; ++q) qr = qr * X[(b >> (8 * q)) & 255u];
-            Qj -= r.revf[j] * qr;
+            Qj -= qr;
         }
 #pragma unroll
         for (int k = 0; k < NSM; ++k) wk[k] += r.nud[j][k] * Qj;

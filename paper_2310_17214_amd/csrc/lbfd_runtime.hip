@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <string>
 #include <vector>
@@ -240,14 +241,17 @@ Par<R> build_par(const lbfd_ctx* c) {
                 orr += c->mech.nu_r[j * c->ns + k];
             }
             if ((of <= 2 && orr <= 2) != (seg == 0)) continue;
+            // FP32: exponents in base 2 (theta and ln K_c scaled by log2 e)
+            const double l2e = sizeof(R) == 4 ? 1.4426950408889634 : 1.0;
             x.A[e] = (R)c->mech.A[j];
             x.beta[e] = (R)c->mech.beta[j];
-            x.theta[e] = (R)c->mech.theta[j];
+            x.theta[e] = (R)(c->mech.theta[j] * l2e);
             x.rev[e] = c->mech.rev[j];
-            x.revf[e] = (R)x.rev[e];
             if (x.rev[e]) {
-                x.lnKc_a[e] = (R)c->mech.lnKc_a[j];
-                x.lnKc_b[e] = (R)c->mech.lnKc_b[j];
+                x.lnKc_a[e] = (R)(c->mech.lnKc_a[j] * l2e);
+                x.lnKc_b[e] = (R)(c->mech.lnKc_b[j] * l2e);
+            } else {
+                x.lnKc_a[e] = std::numeric_limits<R>::infinity();  // reverse term exactly 0
             }
             uint32_t fw = 0, rw = 0;
             int nf = 0, nr = 0;
