@@ -57,6 +57,7 @@ struct Par {
     R rho_ref;        // rho_in * T_in / Mbar_in  (EOS numerator)
     R theta_ign, h_sub;
     R u_in[3], F_b[3];
+    R inlet_eq[19];   // rho_in c_s^2 e_j(u_in): the inlet equilibria less their P_h part
     R fd_face[6][1 + MAXS];
     R rD_fac[MAXS];   // 1/(cp Le_k)
     R M[MAXS], invM[MAXS], dhf[MAXS], mu_star[MAXS];

@@ -203,6 +203,19 @@ Par<R> build_par(const lbfd_ctx* c) {
         P.u_in[a] = (R)(a < c->dim ? p.u_in[a] : 0.0);
         P.F_b[a] = (R)(a < c->dim ? p.body_force[a] : 0.0);
     }
+    {
+        const double u0 = p.u_in[0], u1 = c->dim > 1 ? p.u_in[1] : 0.0,
+                     u2 = c->dim > 2 ? p.u_in[2] : 0.0;
+        const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+        for (int j = 0; j < c->Q; ++j) {
+            const int* cx = c->dim == 2 ? Lat<2>::cx : Lat<3>::cx;
+            const int* cy = c->dim == 2 ? Lat<2>::cy : Lat<3>::cy;
+            const int* cz = c->dim == 2 ? Lat<2>::cz : Lat<3>::cz;
+            const double cu = cx[j] * u0 + cy[j] * u1 + cz[j] * u2;
+            const double e = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+            P.inlet_eq[j] = (R)(p.rho_in * (1.0 / 3.0) * e);
+        }
+    }
     double im_in = 0.0;
     int corr = 0;
     for (int k = 0; k < c->ns; ++k) {
