@@ -82,3 +82,20 @@ def test_bytes_per_cell_formula():
     s * (2Q + 2 + 2 ns + 2 + 1) -- populations and T, Y, divu read and written
     once, phi read once."""
     assert 4 * (2 * 19 + 2 + 2 * 4 + 2 + 1) == 204
+
+
+def test_largest_grids():
+    """The 1024x256x256 elongated bed (D3Q19, FP32, 9 species) fits the
+    indexing limits and its workspace is what the layout says (about 209 B
+    per cell); a grid with more than 2^31 population slots is rejected."""
+    L = lbfd.lib()
+    n = C.c_size_t()
+    big = dict(dim=3, nx=1024, ny=256, nz=256, precision=lbfd.FP32, n_species=9)
+    g = _grid(**big)
+    for f in range(6):
+        g.lb_bc[f] = g.fd_bc[f] = 0
+    assert L.lbfd_workspace_bytes(C.byref(g), C.byref(n)) == 0
+    cells = 1024 * 256 * 256
+    assert 200 * cells < n.value < 220 * cells
+    g.nx, g.ny, g.nz = 1024, 1024, 128  # 19 x 134 M slots > 2^31
+    assert L.lbfd_workspace_bytes(C.byref(g), C.byref(n)) == lbfd.LBFD_E_INVAL
