@@ -148,7 +148,7 @@ BF16_PEAK_TFLOPS = 2500.0
 
 
 def surrogate_measure(wl=None, steps=200, seed=4, log=None, sample_steps=5000, every=25,
-                      per_snapshot=10000, err_steps=1000, sweep=True):
+                      per_snapshot=10000, err_steps=1000, sweep=True, epochs=20):
     """Surrogate against exact chemistry, by default on the 9-species sphere
     bed (256x128x128): train on pairs sampled from an exact run (every 25th
     step of 5000, 10,000 cells each, 90/10 split), then time both paths and
@@ -170,7 +170,7 @@ def surrogate_measure(wl=None, steps=200, seed=4, log=None, sample_steps=5000, e
     n_pairs = int(x.shape[0])
     del x, y
     t1 = time.perf_counter()
-    w, nrm, env, losses = SG.train(xt, yt, ns, epochs=6, batch=8192, seed=seed + 2, log=log)
+    w, nrm, env, losses = SG.train(xt, yt, ns, epochs=epochs, batch=8192, seed=seed + 2, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     res = {}
@@ -235,6 +235,8 @@ def surrogate_measure(wl=None, steps=200, seed=4, log=None, sample_steps=5000, e
         "speedup": round(ex["ms"] / su["ms"], 4),
         f"max_rel_T_err_{err_steps}_steps": err, "T_err_bar": 0.01,
         "fallback_share": su["diag"]["n_fallback"] / (float(err_steps) * wl.cells),
+        "fallback_reason_share": {k: v / (float(err_steps) * wl.cells)
+                                  for k, v in su["diag"]["n_fallback_reason"].items()},
         "kernels_ms": {"exact": {k: round(v[1], 5) for k, v in ex["kt"].items()},
                        "surrogate": {k: round(v[1], 5) for k, v in su["kt"].items()}},
         "mlp_roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS,

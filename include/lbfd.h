@@ -133,6 +133,9 @@ typedef struct {
     double kinetic;                       /* sum rho |u|^2/2 of the last LB step     */
     double umax, Tmin, Tmax;
     int64_t n_nonfinite, n_tau_bad, n_negY, n_flagged_fp64, n_fallback, step;
+    int64_t n_fallback_reason[4];         /* surrogate cell-steps failing each check:
+                                             envelope, overdraw, residual, positivity
+                                             (a cell may fail several)               */
 } lbfd_diag;
 
 typedef enum {

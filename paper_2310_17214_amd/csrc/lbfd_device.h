@@ -20,8 +20,10 @@ constexpr int ISLAND_WG = 1024;        // workgroups (and diagnostics slots) of 
 enum {
     DG_MASS = 0, DG_SP = 1, DG_ENTH = 17, DG_KIN = 18, DG_UMAX = 19, DG_TMIN = 20,
     DG_TMAX = 21, DG_NONFIN = 22, DG_TAUBAD = 23, DG_NEGY = 24, DG_FLAG = 25, DG_FALLBACK = 26,
-    DG_COUNT = 27
+    DG_FB_REASON = 27,  // four counters: envelope, overdraw, residual, positivity
+    DG_COUNT = 31
 };
+static_assert(DG_COUNT <= DIAG_STRIDE, "diagnostic slot layout");
 enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INLET = 2, BC_OUTLET = 3 };
 enum { FD_PERIODIC = 0, FD_DIRICHLET = 1, FD_NEUMANN = 2 };
 enum { PH_LB = 1, PH_FD = 2, PH_CHEM = 4 };

@@ -819,6 +819,7 @@ lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
     out->n_negY = (int64_t)h[DG_NEGY];
     out->n_flagged_fp64 = (int64_t)h[DG_FLAG];
     out->n_fallback = (int64_t)h[DG_FALLBACK];
+    for (int b = 0; b < 4; ++b) out->n_fallback_reason[b] = (int64_t)h[DG_FB_REASON + b];
     out->step = c->steps;
     if (out->n_nonfinite > 0) return fail(c, LBFD_E_NUMERIC, "non-finite values in the state");
     return LBFD_OK;

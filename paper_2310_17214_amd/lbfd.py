@@ -77,7 +77,8 @@ class Diag(C.Structure):
                 ("enthalpy", C.c_double), ("kinetic", C.c_double), ("umax", C.c_double),
                 ("Tmin", C.c_double), ("Tmax", C.c_double), ("n_nonfinite", C.c_int64),
                 ("n_tau_bad", C.c_int64), ("n_negY", C.c_int64), ("n_flagged_fp64", C.c_int64),
-                ("n_fallback", C.c_int64), ("step", C.c_int64)]
+                ("n_fallback", C.c_int64), ("step", C.c_int64),
+                ("n_fallback_reason", C.c_int64 * 4)]
 
 
 _lib = None
@@ -292,8 +293,11 @@ class Context:
         st = lib().lbfd_diagnostics(self._h, C.byref(d))
         if st != LBFD_OK and not (allow_numeric and st == LBFD_E_NUMERIC):
             self._check(st)
-        out = {k: getattr(d, k) for k, _ in Diag._fields_ if k != "species_mass"}
+        out = {k: getattr(d, k) for k, _ in Diag._fields_
+               if k not in ("species_mass", "n_fallback_reason")}
         out["species_mass"] = np.array(d.species_mass[: self.ns])
+        out["n_fallback_reason"] = dict(zip(("envelope", "overdraw", "residual", "positivity"),
+                                            list(d.n_fallback_reason)))
         out["status"] = st
         return out
 
