@@ -148,6 +148,7 @@ def test_s4_forced_fallback_equals_the_exact_path_bitwise():
         assert np.array_equal(a[k], b[k]), k
     d = ctx.diagnostics()
     assert d["n_fallback"] == 3 * ctx.N and d["n_flagged_fp64"] == 3 * ctx.N
+    assert d["n_fallback_reason"]["envelope"] == 3 * ctx.N  # every cell is outside
     dr = ref.diagnostics()
     assert d["mass"] == pytest.approx(dr["mass"], rel=1e-13)
 
