@@ -17,6 +17,8 @@ constexpr int BLOCK = 256;       // threads per workgroup: 4 wave64
 constexpr int DIAG_STRIDE = 32;  // doubles of partials per workgroup
 constexpr int FLAG_GROUP = 4 * BLOCK;  // FP64-island mask words per scan group
 constexpr int ISLAND_WG = 1024;        // workgroups (and diagnostics slots) of the island
+constexpr int FANY = 256;              // "some cell flagged" words (spread to avoid contention)
+static_assert(FANY <= BLOCK && (FANY & (FANY - 1)) == 0, "flag words: one per thread");
 enum {
     DG_MASS = 0, DG_SP = 1, DG_ENTH = 17, DG_KIN = 18, DG_UMAX = 19, DG_TMIN = 20,
     DG_TMAX = 21, DG_NONFIN = 22, DG_TAUBAD = 23, DG_NEGY = 24, DG_FLAG = 25, DG_FALLBACK = 26,
@@ -332,6 +334,7 @@ struct StepArgs {
     int* gtot;            // [groups] flagged cells per group of mask words
     int* list;            // [N] flagged cell indices in mask order
     int* count;           // [1] number of listed cells
+    int* fany;            // [FANY] set to 1 by waves with flagged cells (reset by the island)
     int P_nx, P_ny;       // grid extents (for the list kernel)
     // base of every plane, filled per launch: separate kernel arguments keep
     // each plane's base in scalar registers, so an access costs one shared

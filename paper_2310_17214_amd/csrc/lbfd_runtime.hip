@@ -30,8 +30,8 @@ struct HostMech {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, woff, gtot, list, count, parf, pard,
-        scratch, red, sw, sp, total;
+    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, woff, gtot, list, count, fany, parf,
+        pard, scratch, red, sw, sp, total;
     int nslots;                   // diagnostics slots: step tiles, then island workgroups
     int nbx, nby, zc, nblocks, grid;  // step kernel: 64 x TH tiles of one plane,
                                       // grid padded to a multiple of the 8 XCDs
@@ -78,6 +78,7 @@ Layout make_layout(const lbfd_grid& gr) {
     L.gtot = take((nwords + FLAG_GROUP - 1) / FLAG_GROUP * sizeof(int));
     L.list = take(N * sizeof(int));
     L.count = take(sizeof(int));
+    L.fany = take(FANY * sizeof(int));
     L.parf = take(sizeof(Par<float>));
     L.pard = take(sizeof(Par<double>));
     L.scratch = take(5 * N * sizeof(double));
@@ -88,8 +89,13 @@ Layout make_layout(const lbfd_grid& gr) {
     return L;
 }
 
+// Fixed-order reduction of the partial slots.  Slots from isl0 on belong to
+// the FP64 island: their sums and extrema describe the last step only if it
+// listed cells (*count > 0); their counters always accumulate.
 __global__ void reduce_partials(const double* __restrict__ part, int nblocks, int ns,
-                                double* __restrict__ out) {
+                                double* __restrict__ out, int isl0,
+                                const int* __restrict__ count) {
+    const bool island_live = count != nullptr && *count > 0;
     __shared__ double sh[BLOCK];
     const int t = threadIdx.x;
     for (int s = 0; s < DG_COUNT; ++s) {
@@ -99,7 +105,8 @@ __global__ void reduce_partials(const double* __restrict__ part, int nblocks, in
         }
         const bool mx = s == DG_UMAX || s == DG_TMAX, mn = s == DG_TMIN;
         double acc = mx ? -1e300 : mn ? 1e300 : 0.0;
-        for (int b = t; b < nblocks; b += BLOCK) {
+        const int nb = (s < DG_NONFIN && !island_live) ? min(nblocks, isl0) : nblocks;
+        for (int b = t; b < nb; b += BLOCK) {
             const double v = part[(size_t)b * DIAG_STRIDE + s];
             acc = mx ? fmax(acc, v) : mn ? fmin(acc, v) : acc + v;
         }
@@ -419,6 +426,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.gtot = dptr<int>(c, c->L.gtot);
     a.list = dptr<int>(c, c->L.list);
     a.count = dptr<int>(c, c->L.count);
+    a.fany = dptr<int>(c, c->L.fany);
     a.P_nx = c->grid.nx;
     a.P_ny = c->grid.ny;
     for (int i = 0; i < 19; ++i) a.gpl[i] = i < c->Q ? a.g + (size_t)i * N : a.g;
@@ -691,6 +699,12 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
                                      (size_t)c->L.nslots * DIAG_STRIDE * sizeof(double), c->stream),
                    "clear diagnostics");
     if (st) return st;
+    st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.count), 0, sizeof(int), c->stream),
+                   "clear island count");
+    if (st) return st;
+    st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.fany), 0, FANY * sizeof(int), c->stream),
+                   "clear island flags");
+    if (st) return st;
     st = hip_check(c, hipStreamSynchronize(c->stream), "init");
     if (st) return st;
     c->cur = 0;
@@ -797,9 +811,10 @@ lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
     lbfd_status st = set_device(c);
     if (st) return st;
     double* red = dptr<double>(c, c->L.red);
+    const bool island = c->fp32 && c->ns > 0;
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(BLOCK), 0, c->stream,
-                       dptr<double>(c, c->L.part),
-                       (c->fp32 && c->ns > 0) ? c->L.nslots : c->L.nblocks, c->ns, red);
+                       dptr<double>(c, c->L.part), island ? c->L.nslots : c->L.nblocks, c->ns,
+                       red, c->L.nblocks, island ? dptr<int>(c, c->L.count) : (const int*)nullptr);
     if ((st = hip_check(c, hipGetLastError(), "diagnostics launch"))) return st;
     double h[DG_COUNT];
     st = hip_check(c, hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, c->stream),
