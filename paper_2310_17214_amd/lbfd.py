@@ -232,6 +232,12 @@ class Context:
         self._params = make_params(setup)
         self._check(L.lbfd_set_params(h, C.byref(self._params)))
 
+    def set_params(self, setup):
+        """Re-upload the physical and coupling parameters (same grid and
+        mechanism), e.g. a new ignition threshold between steps."""
+        self._params = make_params(setup)
+        self._check(lib().lbfd_set_params(self._h, C.byref(self._params)))
+
     def _check(self, status, h="self"):
         if status != LBFD_OK:
             handle = self._h if h == "self" else None

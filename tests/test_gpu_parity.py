@@ -406,3 +406,28 @@ def test_degenerate_states(case, precision):
         assert e <= bar, (k, e)
     d = ctx.diagnostics()
     assert d["n_flagged_fp64"] == 0 and d["n_nonfinite"] == 0
+
+
+def test_diagnostics_follow_the_state_across_island_and_quiet_steps():
+    """FP32 9-species crop: steps with cells on the FP64 island, then (the
+    ignition threshold raised) steps with none, where the island kernels do
+    no work: the conservation sums always describe the current state."""
+    wl = _crop9("fp32")
+    ctx = lb().Context(wl.setup, wl.phi)
+    ctx.init_state(wl.T0, wl.Y0)
+
+    def mass_of_state():
+        return float(ctx.read(lb().F_RHO).sum())
+
+    ctx.step(20)
+    d1 = ctx.diagnostics()
+    assert d1["n_flagged_fp64"] > 0
+    assert d1["mass"] == pytest.approx(mass_of_state(), rel=1e-6)
+    quiet = dict(wl.setup, theta_ign=1e30)
+    ctx.set_params(quiet)
+    ctx.step(5)
+    d2 = ctx.diagnostics()
+    say(f"flagged {d1['n_flagged_fp64']} -> {d2['n_flagged_fp64']}, mass {d2['mass']:.9e}")
+    assert d2["n_flagged_fp64"] == d1["n_flagged_fp64"]  # cumulative, none added
+    assert d2["mass"] == pytest.approx(mass_of_state(), rel=1e-6)
+    assert d2["Tmin"] > 0.0
