@@ -115,6 +115,8 @@ template <> __device__ __forceinline__ double flog<double>(double x) { return lo
 
 // ----------------------------------------------------------------- closures
 // Ideal-gas density at fixed thermodynamic pressure: rho = rho_in (T_in/T)(M/M_in).
+// The sums run over the kernel's species bucket: a padding species has Y = 0
+// and 1/M = 0, so it adds an exact zero (no branch on the species count).
 template <typename R, int NSM>
 __device__ __forceinline__ R eos(const Par<R>& P, R T, const R* Y) {
     if constexpr (NSM == 0) {
@@ -122,8 +124,7 @@ __device__ __forceinline__ R eos(const Par<R>& P, R T, const R* Y) {
     } else {
         R im = R(0);
 #pragma unroll
-        for (int k = 0; k < NSM; ++k)
-            if (k < P.ns) im += Y[k] * P.invM[k];
+        for (int k = 0; k < NSM; ++k) im += Y[k] * P.invM[k];
         return dvd(P.rho_ref, T * im);
     }
 }
@@ -144,11 +145,10 @@ __device__ __forceinline__ void transport(const Par<R>& P, R T, const R* Y, R& m
         if (P.transport != 0) {
             R X[LBFD_NA(NSM)], im = R(0);
 #pragma unroll
-            for (int k = 0; k < NSM; ++k)
-                if (k < P.ns) im += Y[k] * P.invM[k];
+            for (int k = 0; k < NSM; ++k) im += Y[k] * P.invM[k];
             R mbar = rcp(im);
 #pragma unroll
-            for (int k = 0; k < NSM; ++k) X[k] = (k < P.ns) ? Y[k] * mbar * P.invM[k] : R(0);
+            for (int k = 0; k < NSM; ++k) X[k] = Y[k] * mbar * P.invM[k];
             R m = R(0), l1 = R(0), l2 = R(0);
 #pragma unroll
             for (int k = 0; k < NSM; ++k) {
