@@ -57,6 +57,8 @@ def make_workload(name):
         return W.cylinder_channel()
     if name == "sphere_bed_9sp":
         return W.bed_sphere_9sp(precision="fp32")
+    if name == "superquadric_bed":
+        return W.bed_superquadric_9sp(precision="fp32")
     if name == "elongated_bed_slab":
         # one GPU's share (third of eight 128-cell slabs, with a halo plane
         # on each side) of the 1024x256x256 elongated bed
