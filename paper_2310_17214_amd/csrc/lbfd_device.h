@@ -16,9 +16,8 @@ constexpr int MAXR_TAB = MAXR + 2;  // reaction table entries: two segments, eac
 constexpr int BLOCK = 256;       // threads per workgroup: 4 wave64
 constexpr int DIAG_STRIDE = 32;  // doubles of partials per workgroup
 constexpr int FLAG_GROUP = 4 * BLOCK;  // FP64-island mask words per scan group
+constexpr int GSPREAD = 16;            // counters per group (word w adds to counter w % GSPREAD)
 constexpr int ISLAND_WG = 1024;        // workgroups (and diagnostics slots) of the island
-constexpr int FANY = 256;              // "some cell flagged" words (spread to avoid contention)
-static_assert(FANY <= BLOCK && (FANY & (FANY - 1)) == 0, "flag words: one per thread");
 enum {
     DG_MASS = 0, DG_SP = 1, DG_ENTH = 17, DG_KIN = 18, DG_UMAX = 19, DG_TMIN = 20,
     DG_TMAX = 21, DG_NONFIN = 22, DG_TAUBAD = 23, DG_NEGY = 24, DG_FLAG = 25, DG_FALLBACK = 26,
@@ -330,11 +329,10 @@ struct StepArgs {
     int diag;             // write diagnostics partials
     int sur;              // FP32 surrogate mode: reactions left to the surrogate kernels
     // FP32 mode: compaction of the cells flagged for the FP64 reaction step
-    int* woff;            // [nblocks * 4] offsets of the mask words within their group
-    int* gtot;            // [groups] flagged cells per group of mask words
+    int* gtot;            // [groups][GSPREAD] flagged cells per group of mask words (added
+                          // by the kernels that write the masks, cleared by the island)
     int* list;            // [N] flagged cell indices in mask order
     int* count;           // [1] number of listed cells
-    int* fany;            // [FANY] set to 1 by waves with flagged cells (reset by the island)
     int P_nx, P_ny;       // grid extents (for the list kernel)
     // base of every plane, filled per launch: separate kernel arguments keep
     // each plane's base in scalar registers, so an access costs one shared

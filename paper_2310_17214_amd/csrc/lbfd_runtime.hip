@@ -30,9 +30,10 @@ struct HostMech {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, woff, gtot, list, count, fany, parf,
+    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, gtot, list, count, parf,
         pard, scratch, red, sw, sp, total;
     int nslots;                   // diagnostics slots: step tiles, then island workgroups
+    int ngroups;                  // groups of FP64-island mask words
     int nbx, nby, zc, nblocks, grid;  // step kernel: 64 x TH tiles of one plane,
                                       // grid padded to a multiple of the 8 XCDs
     int nlin;                     // one-cell-per-thread kernels
@@ -74,11 +75,10 @@ Layout make_layout(const lbfd_grid& gr) {
     L.part = take((size_t)L.nslots * DIAG_STRIDE * sizeof(double));
     const size_t nwords = (size_t)L.nblocks * (BLOCK / 64);
     L.flags = take(nwords * sizeof(unsigned long long));
-    L.woff = take(nwords * sizeof(int));
-    L.gtot = take((nwords + FLAG_GROUP - 1) / FLAG_GROUP * sizeof(int));
+    L.ngroups = (int)((nwords + FLAG_GROUP - 1) / FLAG_GROUP);
+    L.gtot = take((size_t)L.ngroups * GSPREAD * sizeof(int));
     L.list = take(N * sizeof(int));
     L.count = take(sizeof(int));
-    L.fany = take(FANY * sizeof(int));
     L.parf = take(sizeof(Par<float>));
     L.pard = take(sizeof(Par<double>));
     L.scratch = take(5 * N * sizeof(double));
@@ -422,11 +422,9 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.phase = phase;
     a.diag = 1;
     a.sur = sizeof(R) == 4 && c->sur && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM);
-    a.woff = dptr<int>(c, c->L.woff);
     a.gtot = dptr<int>(c, c->L.gtot);
     a.list = dptr<int>(c, c->L.list);
     a.count = dptr<int>(c, c->L.count);
-    a.fany = dptr<int>(c, c->L.fany);
     a.P_nx = c->grid.nx;
     a.P_ny = c->grid.ny;
     for (int i = 0; i < 19; ++i) a.gpl[i] = i < c->Q ? a.g + (size_t)i * N : a.g;
@@ -702,8 +700,9 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
     st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.count), 0, sizeof(int), c->stream),
                    "clear island count");
     if (st) return st;
-    st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.fany), 0, FANY * sizeof(int), c->stream),
-                   "clear island flags");
+    st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.gtot), 0,
+                                     (size_t)c->L.ngroups * GSPREAD * sizeof(int), c->stream),
+                   "clear island group counts");
     if (st) return st;
     st = hip_check(c, hipStreamSynchronize(c->stream), "init");
     if (st) return st;
