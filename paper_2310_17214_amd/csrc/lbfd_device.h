@@ -58,12 +58,15 @@ struct Par {
     int lb_bc[6], fd_bc[6];
     R A_u, A_T, inv_eta2, T_s, cp, inv_cp, inv_Pr, rho_in, T_in, mu_ref, S_T_in, S;
     R rho_ref;        // rho_in * T_in / Mbar_in  (EOS numerator)
+    R inv_T_in;       // 1 / T_in, rounded once on the host
     R theta_ign, h_sub;
     R u_in[3], F_b[3];
     R inlet_eq[19];   // rho_in c_s^2 e_j(u_in): the inlet equilibria less their P_h part
     R fd_face[6][1 + MAXS];
     R rD_fac[MAXS];   // 1/(cp Le_k)
     R M[MAXS], invM[MAXS], dhf[MAXS], mu_star[MAXS];
+    R inv_mu_star[MAXS];  // 1 / mu_star (mu_star = 1 for padding species)
+    R Pr_over_cp;         // Pr / cp
     R Phi[MAXS][MAXS];
     Rxn<R> rx;
 };
@@ -132,7 +135,13 @@ __device__ __forceinline__ R eos(const Par<R>& P, R T, const R* Y) {
 template <typename R>
 __device__ __forceinline__ R sutherland(const Par<R>& P, R T) {
     if (P.mu_model == 0) return R(1);
-    R x = dvd(T, P.T_in);
+    // FP32: the reciprocal of the constant comes from the host (no per-cell
+    // reciprocal); FP64: the division as written
+    R x;
+    if constexpr (sizeof(R) == 4)
+        x = T * P.inv_T_in;
+    else
+        x = dvd(T, P.T_in);
     return dvd(x * fsqrt(x) * P.S_T_in, T + P.S);
 }
 
@@ -149,18 +158,26 @@ __device__ __forceinline__ void transport(const Par<R>& P, R T, const R* Y, R& m
 #pragma unroll
             for (int k = 0; k < NSM; ++k) X[k] = Y[k] * mbar * P.invM[k];
             R m = R(0), l1 = R(0), l2 = R(0);
+            // FP32: 1/lambda_k = (1/mu*_k) (1/mu0) (Pr/cp), one reciprocal per
+            // state instead of one per species
+            R inv_l0 = R(0);
+            if constexpr (sizeof(R) == 4) inv_l0 = rcp(mu0) * P.Pr_over_cp;
+            // The sums run over the species bucket: a padding species has
+            // X = 0, mu* = 1 and a row of ones in Phi (its denominator is then
+            // sum X = 1), so every term it adds is an exact zero.
 #pragma unroll
             for (int k = 0; k < NSM; ++k) {
-                if (k >= P.ns) continue;
                 R den = R(0);
 #pragma unroll
-                for (int j = 0; j < NSM; ++j)
-                    if (j < P.ns) den += P.Phi[k][j] * X[j];
+                for (int j = 0; j < NSM; ++j) den += P.Phi[k][j] * X[j];
                 R muk = P.mu_star[k] * mu0;
                 R lamk = muk * P.cp * P.inv_Pr;
                 m += dvd(muk * X[k], den);
                 l1 += X[k] * lamk;
-                l2 += dvd(X[k], lamk);
+                if constexpr (sizeof(R) == 4)
+                    l2 += X[k] * (P.inv_mu_star[k] * inv_l0);
+                else
+                    l2 += dvd(X[k], lamk);
             }
             mu = m;
             lam = R(0.5) * (l1 + rcp(l2));

@@ -201,6 +201,7 @@ Par<R> build_par(const lbfd_ctx* c) {
     P.inv_Pr = (R)(1.0 / p.Pr);
     P.rho_in = (R)p.rho_in;
     P.T_in = (R)p.T_in;
+    P.inv_T_in = (R)(1.0 / p.T_in);
     P.mu_ref = (R)(p.rho_in * p.nu_in);
     P.S = (R)p.sutherland_S;
     P.S_T_in = (R)(p.T_in + p.sutherland_S);
@@ -243,6 +244,15 @@ Par<R> build_par(const lbfd_ctx* c) {
         for (int j = 0; j < c->ns; ++j)
             P.Phi[k][j] =
                 (R)wilke(c->mech.mu_star[k], c->mech.mu_star[j], c->mech.M[k], c->mech.M[j]);
+    // padding species: mu* = 1 and a row of ones in Phi (denominator
+    // sum X = 1), so that their X = 0 adds exact zeros to the Wilke sums
+    for (int k = c->ns; k < MAXS; ++k) {
+        P.mu_star[k] = (R)1;
+        for (int j = 0; j < MAXS; ++j) P.Phi[k][j] = (R)1;
+    }
+    for (int k = 0; k < MAXS; ++k)
+        P.inv_mu_star[k] = k < c->ns ? (R)(1.0 / c->mech.mu_star[k]) : (R)1;
+    P.Pr_over_cp = (R)(p.Pr / p.cp);
     // The reaction table: reactions whose sides have at most two factors
     // first, then the others, each segment in the mechanism's order and
     // padded to the kernel's reaction group; index words pad with the
