@@ -61,7 +61,7 @@ typedef enum {
     LBFD_E_DEVICE = -3,      /* HIP runtime error                                */
     LBFD_E_STATE = -4,       /* call out of order (e.g. step before init_state)  */
     LBFD_E_NUMERIC = -5,     /* non-finite values appeared in a step             */
-    LBFD_E_UNSUPPORTED = -6  /* valid request this build does not implement      */
+    LBFD_E_UNSUPPORTED = -6  /* valid request the library does not implement     */
 } lbfd_status;
 
 typedef enum { LBFD_FP64 = 0, LBFD_FP32 = 1 } lbfd_precision;
