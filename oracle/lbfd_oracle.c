@@ -60,6 +60,7 @@ struct orc_ctx {
     double *phi, *g, *gs, *T, *Y, *divu;
     double *u, *Ph, *rho_n, *Tst, *Yst, *qT;
     double diag[ORC_D_LEN];
+    double m0, p_prev;               /* closed domain: mass, previous P0 / P0_in */
 };
 
 static long cidx(const orc_ctx* o, int x, int y, int z) {
@@ -77,10 +78,30 @@ static double inv_mbar(const orc_setup* s, const double* Y) {
     return r;
 }
 double orc_eos(const orc_setup* s, double T, const double* Y) {
-    if (s->ns == 0) return s->rho_in * (s->T_in / T);
+    /* a closed domain scales the density with P0(t) / P0_in */
+    const double p = s->closed ? s->p0 : 1.0;
+    if (s->ns == 0) return p * (s->rho_in * (s->T_in / T));
     double mbar = 1.0 / inv_mbar(s, Y);
     double mbar_in = 1.0 / inv_mbar(s, s->Y_in);
-    return s->rho_in * (s->T_in / T) * (mbar / mbar_in);
+    return p * (s->rho_in * (s->T_in / T) * (mbar / mbar_in));
+}
+
+/* Closed domain (Sec. 3.1): the mass m = int rho dV is fixed and the EOS makes
+ * rho proportional to P0 M / T, so P0 = m R / int (M / T) dV.  With the
+ * reference P0_in = rho_in r T_in / M_in (r = R / M_ref, M in units of M_ref)
+ * the ratio is p = m M_in / (rho_in T_in sum_cells M / T), the sum running over
+ * every cell of the diffuse-interface domain, in cell order.               */
+static double closed_p0(const orc_ctx* o) {
+    const orc_setup* s = &o->s;
+    double S = 0.0;
+    for (long id = 0; id < o->N; ++id) {
+        double Y[ORC_MAXS];
+        for (int k = 0; k < s->ns; ++k) Y[k] = o->Y[(long)k * o->N + id];
+        const double mbar = s->ns ? 1.0 / inv_mbar(s, Y) : 1.0;
+        S += mbar / o->T[id];
+    }
+    const double mbar_in = s->ns ? 1.0 / inv_mbar(s, s->Y_in) : 1.0;
+    return o->m0 * mbar_in / (s->rho_in * s->T_in * S);
 }
 
 /* Sutherland law (Sec. 4, Eq. muT) written as a ratio to the inlet state so
@@ -413,9 +434,19 @@ static void fd_cell(const orc_ctx* o, int x, int y, int z, const double* u, doub
         }
     }
     double qT = (lapT + H * (s->T_s - Tc)) / (rho_c * s->cp);
+    double dlnp = 0.0;
+    if (s->closed) {
+        /* dP0/dt (Eq. energy-transport-DI-version), explicit: the change of
+         * P0 over the previous step, P0_in (p^n - p^{n-1}) per unit time */
+        const double mbar_in = ns ? 1.0 / inv_mbar(s, s->Y_in) : 1.0;
+        const double P0_in = s->rho_in * s->r_gas * s->T_in / mbar_in;
+        qT += P0_in * (s->p0 - o->p_prev) / (rho_c * s->cp);
+        dlnp = (s->p0 - o->p_prev) / s->p0;
+    }
     *Tout = Tc + (qT - advT);
     for (int k = 0; k < ns; ++k) Yout[k] = Yc[k] + (J[k] / rho_c - advY[k]);
-    *qTout = qT / Tc;
+    /* thermal divergence (1/T) DT/Dt, less (1/P0) dP0/dt in a closed domain */
+    *qTout = qT / Tc - dlnp;
 }
 
 static void fd_phase(orc_ctx* o, int zero_u) {
@@ -615,6 +646,9 @@ void orc_destroy(orc_ctx* o) {
  * not applied at t = 0).                                                     */
 int orc_init_state(orc_ctx* o, const double* T, const double* Y, const double* u) {
     const orc_setup* s = &o->s;
+    o->s.p0 = 1.0; /* a closed domain starts at P0 = P0_in */
+    o->p_prev = 1.0;
+    o->m0 = 0.0;
     for (long id = 0; id < o->N; ++id) {
         double Yc[ORC_MAXS], uc[3] = {0.0, 0.0, 0.0}, geq[19];
         o->T[id] = T[id];
@@ -627,6 +661,7 @@ int orc_init_state(orc_ctx* o, const double* T, const double* Y, const double* u
         o->divu[id] = 0.0;
         for (int a = 0; a < 3; ++a) o->u[(long)a * o->N + id] = uc[a];
         o->rho_n[id] = rho;
+        o->m0 += rho; /* the closed domain's mass, in cell order */
     }
     for (int k = 0; k < ORC_D_LEN; ++k) o->diag[k] = 0.0;
     reduce_phase(o, 0); /* snapshot sums of the initial state; counters start at zero */
@@ -662,9 +697,15 @@ int orc_step(orc_ctx* o, int32_t n, int32_t mask) {
         chem_phase(o, (mask & ORC_PH_CHEM) != 0);
         reduce_phase(o, 1);
         o->diag[ORC_D_STEP] += 1.0;
+        if (o->s.closed) {  /* P0 of the new state, for the next step */
+            o->p_prev = o->s.p0;
+            o->s.p0 = closed_p0(o);
+        }
     }
     return 0;
 }
+
+double orc_p0(const orc_ctx* o) { return o->s.closed ? o->s.p0 : 1.0; }
 
 int orc_fd_only(orc_ctx* o, double* Tstar, double* Ystar) {
     fd_phase(o, 1);

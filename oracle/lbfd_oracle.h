@@ -57,6 +57,11 @@ typedef struct {
     double  A[ORC_MAXR], beta[ORC_MAXR], theta[ORC_MAXR];
     int32_t rev[ORC_MAXR];
     double  lnKc_a[ORC_MAXR], lnKc_b[ORC_MAXR];
+    /* closed domain (Sec. 3.1, the P0(t) of Eq. rho-in-terms-of-P0-and-T and
+     * the dP0/dt term of Eq. energy-transport-DI-version): 0 keeps P0 fixed */
+    int32_t closed;
+    double  r_gas;                    /* R / M_ref in the units of cp            */
+    double  p0;                       /* P0 / P0_in, kept by the oracle          */
 } orc_setup;
 
 typedef struct orc_ctx orc_ctx;
@@ -84,5 +89,7 @@ double orc_eos(const orc_setup* s, double T, const double* Y);
 void orc_reactor(const orc_setup* s, double* T, double* Y, int32_t nsteps);
 /* fd phase alone with u forced to zero (conservation pin); writes T*, Y* */
 int  orc_fd_only(orc_ctx* o, double* Tstar, double* Ystar);
+/* thermodynamic pressure ratio P0 / P0_in of the current state */
+double orc_p0(const orc_ctx* o);
 
 #endif

@@ -43,6 +43,7 @@ class Setup(C.Structure):
         ("nu_f", (C.c_int32 * MAXS) * MAXR), ("nu_r", (C.c_int32 * MAXS) * MAXR),
         ("A", C.c_double * MAXR), ("beta", C.c_double * MAXR), ("theta", C.c_double * MAXR),
         ("rev", C.c_int32 * MAXR), ("lnKc_a", C.c_double * MAXR), ("lnKc_b", C.c_double * MAXR),
+        ("closed", C.c_int32), ("r_gas", C.c_double), ("p0", C.c_double),
     ]
 
 
@@ -81,6 +82,8 @@ def lib():
         L.orc_eos.argtypes = [C.POINTER(Setup), C.c_double, dp]
         L.orc_reactor.argtypes = [C.POINTER(Setup), dp, dp, C.c_int32]
         L.orc_fd_only.argtypes = [C.c_void_p, dp, dp]
+        L.orc_p0.restype = C.c_double
+        L.orc_p0.argtypes = [C.c_void_p]
         _lib = L
     return _lib
 
@@ -120,6 +123,9 @@ def make_setup(s: dict) -> Setup:
         st.A[j], st.beta[j], st.theta[j] = mech["A"][j], mech["beta"][j], mech["theta"][j]
         st.rev[j] = mech["rev"][j]
         st.lnKc_a[j], st.lnKc_b[j] = mech["lnKc_a"][j], mech["lnKc_b"][j]
+    st.closed = int(s.get("closed", 0))
+    st.r_gas = float(s.get("r_gas", 0.0))
+    st.p0 = 1.0
     return st
 
 
@@ -180,6 +186,10 @@ class Oracle:
         out = np.empty(D_LEN, np.float64)
         lib().orc_diag(self._h, _dp(out))
         return out
+
+    def p0(self):
+        """P0 / P0_in of the current state (1 unless the domain is closed)."""
+        return float(lib().orc_p0(self._h))
 
     def fd_only(self):
         Ts = np.empty(self.N)

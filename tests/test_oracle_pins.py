@@ -333,6 +333,43 @@ def test_P8_adiabatic_flame_temperature_one_step():
     assert np.abs(o.fields()["u"]).max() < 1e-14
 
 
+def test_P18_closed_box_constant_volume_flame_temperature():
+    """Closed periodic box, one-step F + O -> 2P with Q/cp = 2000 K and all
+    M = 1: with P0(t) from the fixed mass and the dP0/dt term in the
+    temperature equation (Sec. 3.1, Eqs. rho-in-terms-of-P0-and-T and
+    energy-transport-DI-version), the uniform gas burns at constant density,
+    so rho (cp - r) dT = dQ and T ends at T0 + Y_F0 (Q/cp) cp / (cp - r);
+    P0 / P0_in ends at T_end / T0 and the domain's mass stays fixed."""
+    mech = W.mech_one_step(A=W.one_step_rate_constant())
+    Y0 = [0.05, 0.5, 0.35, 0.1]
+    s = _reactor_setup(mech, Y0)
+    cp = s["cp"]
+    s["closed"], s["r_gas"] = 1, 0.3 * cp
+    shape = (2, 2, 2)
+    o = O.Oracle(s, np.zeros(shape))
+    T0 = 1000.0
+    o.init_state(np.full(shape, T0), np.array(Y0)[:, None, None, None] * np.ones((4,) + shape))
+    m0 = o.read(O.F_RHO).sum()
+    for _ in range(300):
+        o.step(10)
+        # P0 is set from the new state so that the domain keeps its mass
+        assert abs(o.read(O.F_RHO).sum() - m0) <= 1e-13 * m0
+        if o.read(O.F_Y, 0).max() < 1e-13:
+            break
+    o.step(50)  # the lagged dP0/dt term settles geometrically (ratio r/cp)
+    T_end = T0 + 2000.0 * Y0[0] * cp / (cp - 0.3 * cp)
+    T = o.read(O.F_T)
+    assert rel(T, np.full(shape, T_end)) <= 1e-9
+    assert abs(o.p0() - T_end / T0) <= 1e-9 * T_end / T0
+    # an open box (the same run with P0 fixed) ends at the isobaric T_ad instead
+    s["closed"] = 0
+    o2 = O.Oracle(s, np.zeros(shape))
+    o2.init_state(np.full(shape, T0), np.array(Y0)[:, None, None, None] * np.ones((4,) + shape))
+    o2.step(3050)
+    assert rel(o2.read(O.F_T), np.full(shape, T0 + 2000.0 * Y0[0])) <= 1e-9
+    assert o2.p0() == 1.0
+
+
 def test_P11_reaction_enthalpy_per_substep():
     """Every explicit sub-step conserves cp T + sum_k dh_f,k Y_k (Eq. 9)
     and the total mass fraction (element-balanced reactions, Eq. 8)."""
