@@ -107,6 +107,16 @@ typedef struct {
     int32_t n_sub;                   /* explicit reaction sub-steps per step (>= 1) */
     double ign_threshold;            /* FP32 mode: a cell's reaction step runs in
                                         FP64 when |omega_T| dt/(rho cp) exceeds it [K] */
+    int32_t closed;                  /* 1: closed domain (Sec. 3.1): the thermodynamic
+                                        pressure P0(t) follows from the fixed mass,
+                                        P0 / P0_in = sum(M/T at init) / sum(M/T), taken
+                                        after every step; it scales the EOS, and its
+                                        change over the previous step enters the
+                                        temperature equation (Eq. energy-transport-
+                                        DI-version) and the thermal divergence.  No
+                                        inlet or outlet face.  0: P0 fixed           */
+    double r_gas;                    /* closed domain: R / M_ref in the units of cp,
+                                        0 <= r_gas < cp                              */
 } lbfd_params;
 
 typedef struct {
@@ -136,6 +146,8 @@ typedef struct {
     int64_t n_fallback_reason[4];         /* surrogate cell-steps failing each check:
                                              envelope, overdraw, residual, positivity
                                              (a cell may fail several)               */
+    double p0_ratio;                      /* P0 / P0_in for the next step (1 unless
+                                             the domain is closed)                   */
 } lbfd_diag;
 
 typedef enum {

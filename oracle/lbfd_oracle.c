@@ -60,7 +60,8 @@ struct orc_ctx {
     double *phi, *g, *gs, *T, *Y, *divu;
     double *u, *Ph, *rho_n, *Tst, *Yst, *qT;
     double diag[ORC_D_LEN];
-    double m0, p_prev;               /* closed domain: mass, previous P0 / P0_in */
+    double p_prev, S0;               /* closed domain: previous P0 / P0_in, and the
+                                        sum of M / T of the initial state        */
 };
 
 static long cidx(const orc_ctx* o, int x, int y, int z) {
@@ -87,21 +88,24 @@ double orc_eos(const orc_setup* s, double T, const double* Y) {
 }
 
 /* Closed domain (Sec. 3.1): the mass m = int rho dV is fixed and the EOS makes
- * rho proportional to P0 M / T, so P0 = m R / int (M / T) dV.  With the
- * reference P0_in = rho_in r T_in / M_in (r = R / M_ref, M in units of M_ref)
- * the ratio is p = m M_in / (rho_in T_in sum_cells M / T), the sum running over
- * every cell of the diffuse-interface domain, in cell order.               */
-static double closed_p0(const orc_ctx* o) {
+ * rho proportional to P0 M / T, so P0 = m R / int (M / T) dV.  With m taken
+ * from the initial state at P0_in, the ratio is p = S0 / S, S = sum over the
+ * cells of M / T (every cell of the diffuse-interface domain).  The sum is
+ * compensated (Neumaier's variant of Kahan summation): dP0/dt is the
+ * difference of two such sums, so their rounding must not depend on the order
+ * in which the cells are added.                                            */
+static double closed_sum(const orc_ctx* o) {
     const orc_setup* s = &o->s;
-    double S = 0.0;
+    double S = 0.0, c = 0.0;
     for (long id = 0; id < o->N; ++id) {
         double Y[ORC_MAXS];
         for (int k = 0; k < s->ns; ++k) Y[k] = o->Y[(long)k * o->N + id];
         const double mbar = s->ns ? 1.0 / inv_mbar(s, Y) : 1.0;
-        S += mbar / o->T[id];
+        const double x = mbar / o->T[id], t = S + x;
+        c += fabs(S) >= fabs(x) ? (S - t) + x : (x - t) + S;
+        S = t;
     }
-    const double mbar_in = s->ns ? 1.0 / inv_mbar(s, s->Y_in) : 1.0;
-    return o->m0 * mbar_in / (s->rho_in * s->T_in * S);
+    return S + c;
 }
 
 /* Sutherland law (Sec. 4, Eq. muT) written as a ratio to the inlet state so
@@ -648,7 +652,6 @@ int orc_init_state(orc_ctx* o, const double* T, const double* Y, const double* u
     const orc_setup* s = &o->s;
     o->s.p0 = 1.0; /* a closed domain starts at P0 = P0_in */
     o->p_prev = 1.0;
-    o->m0 = 0.0;
     for (long id = 0; id < o->N; ++id) {
         double Yc[ORC_MAXS], uc[3] = {0.0, 0.0, 0.0}, geq[19];
         o->T[id] = T[id];
@@ -661,10 +664,10 @@ int orc_init_state(orc_ctx* o, const double* T, const double* Y, const double* u
         o->divu[id] = 0.0;
         for (int a = 0; a < 3; ++a) o->u[(long)a * o->N + id] = uc[a];
         o->rho_n[id] = rho;
-        o->m0 += rho; /* the closed domain's mass, in cell order */
     }
     for (int k = 0; k < ORC_D_LEN; ++k) o->diag[k] = 0.0;
     reduce_phase(o, 0); /* snapshot sums of the initial state; counters start at zero */
+    o->S0 = s->closed ? closed_sum(o) : 0.0;
     return 0;
 }
 
@@ -699,7 +702,7 @@ int orc_step(orc_ctx* o, int32_t n, int32_t mask) {
         o->diag[ORC_D_STEP] += 1.0;
         if (o->s.closed) {  /* P0 of the new state, for the next step */
             o->p_prev = o->s.p0;
-            o->s.p0 = closed_p0(o);
+            o->s.p0 = o->S0 / closed_sum(o);
         }
     }
     return 0;

@@ -57,7 +57,10 @@ struct Par {
     int n_sub, mu_model, transport, corr, any_beta;
     int lb_bc[6], fd_bc[6];
     R A_u, A_T, inv_eta2, T_s, cp, inv_cp, inv_Pr, rho_in, T_in, mu_ref, S_T_in, S;
-    R rho_ref;        // rho_in * T_in / Mbar_in  (EOS numerator)
+    R rho_ref;        // rho_in * T_in / Mbar_in  (EOS numerator), times P0 / P0_in
+                      // in a closed domain (rewritten on the device after each step)
+    R dp0_term;       // closed domain: P0_in (p^n - p^{n-1}), the dP0/dt of the step
+    R dlnp0;          // closed domain: (p^n - p^{n-1}) / p^n
     R inv_T_in;       // 1 / T_in, rounded once on the host
     R theta_ign, h_sub;
     R u_in[3], F_b[3];
@@ -324,6 +327,15 @@ __device__ __forceinline__ void chem_increments(const Par<C>& P, C T0, const C* 
 }
 
 // ------------------------------------------------------------ kernel args
+// Closed domain: P0 / P0_in = p = S0 / S with S = sum over cells of M / T (the
+// domain's mass is fixed and rho is proportional to P0 M / T).
+struct P0State {
+    double S0, p, p_prev;  // sum M / T of the initial state; p of this and the last step
+    double rho_ref0;       // rho_ref at p = 1
+    double P0_in;          // rho_ref0 * r_gas
+};
+constexpr int P0_PARTS = 1024;  // workgroups (and partial sums) of the P0 sum
+
 template <typename R>
 struct StepArgs {
     R* g;                 // [Q][N] populations (AA layout)

@@ -15,6 +15,10 @@ hipError_t launch_step_f32(int dim, int nsm, const StepArgs<float>& a, int grid,
     default: return launch_step_t<float, 16>(dim, a, grid, s);
     }
 }
+hipError_t launch_p0_sum_f32(const float* T, const float* Y, int N, int ns, const Par<float>* P,
+                              double* part, hipStream_t s) {
+    return launch_p0_sum_t<float>(T, Y, N, ns, P, part, s);
+}
 hipError_t launch_macro_f32(int dim, int nsm, const MacroArgs<float>& a, int grid, hipStream_t s) {
     switch (nsm) {
     case 0: return launch_macro_t<float, 0>(dim, a, grid, s);

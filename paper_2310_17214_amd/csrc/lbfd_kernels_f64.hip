@@ -13,6 +13,10 @@ hipError_t launch_step_f64(int dim, int nsm, const StepArgs<double>& a, int grid
     default: return launch_step_t<double, 16>(dim, a, grid, s);
     }
 }
+hipError_t launch_p0_sum_f64(const double* T, const double* Y, int N, int ns, const Par<double>* P,
+                              double* part, hipStream_t s) {
+    return launch_p0_sum_t<double>(T, Y, N, ns, P, part, s);
+}
 hipError_t launch_macro_f64(int dim, int nsm, const MacroArgs<double>& a, int grid, hipStream_t s) {
     switch (nsm) {
     case 0: return launch_macro_t<double, 0>(dim, a, grid, s);

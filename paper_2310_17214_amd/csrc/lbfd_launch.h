@@ -24,6 +24,11 @@ hipError_t launch_mlp_eval_f32(int nsm, const float* T, const float* Y, int n, f
 hipError_t launch_sample_f32(int nsm, const float* T, const float* Y, int N, const int* cells,
                              int n, float* x, float* y, const Par<double>* PD, float p_in,
                              hipStream_t s);
+// closed domain: per-workgroup sums of M / T (P0_PARTS partials)
+hipError_t launch_p0_sum_f32(const float* T, const float* Y, int N, int ns, const Par<float>* P,
+                             double* part, hipStream_t s);
+hipError_t launch_p0_sum_f64(const double* T, const double* Y, int N, int ns,
+                             const Par<double>* P, double* part, hipStream_t s);
 // halo planes of an x face
 hipError_t launch_halo_f32(const HaloArgs<float>& a, hipStream_t s);
 hipError_t launch_halo_f64(const HaloArgs<double>& a, hipStream_t s);

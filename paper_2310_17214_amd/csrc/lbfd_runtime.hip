@@ -30,7 +30,7 @@ struct HostMech {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, gtot, list, count, parf,
+    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, gtot, list, count, p0, p0part, parf,
         pard, scratch, red, sw, sp, total;
     int nslots;                   // diagnostics slots: step tiles, then island workgroups
     int ngroups;                  // groups of FP64-island mask words
@@ -79,6 +79,8 @@ Layout make_layout(const lbfd_grid& gr) {
     L.gtot = take((size_t)L.ngroups * GSPREAD * sizeof(int));
     L.list = take(N * sizeof(int));
     L.count = take(sizeof(int));
+    L.p0 = take(sizeof(P0State));
+    L.p0part = take(2 * P0_PARTS * sizeof(double));
     L.parf = take(sizeof(Par<float>));
     L.pard = take(sizeof(Par<double>));
     L.scratch = take(5 * N * sizeof(double));
@@ -121,6 +123,58 @@ __global__ void reduce_partials(const double* __restrict__ part, int nblocks, in
         }
         if (t == 0) out[s] = sh[0];
         __syncthreads();
+    }
+}
+
+// Closed domain: P0 / P0_in from the partial sums of M / T (mode 0: the initial
+// state, p = 1; mode 1: after a step, p = S0 / S; mode 2: no new sum), then the
+// parameter blocks' EOS numerator and the step's dP0/dt terms for the next step.
+__global__ void p0_update_kernel(const double* __restrict__ part, P0State* __restrict__ st,
+                                 Par<float>* __restrict__ pf, Par<double>* __restrict__ pd,
+                                 int mode) {
+    __shared__ double sh[BLOCK], shc[BLOCK];
+    const int t = threadIdx.x;
+    double acc = 0.0, cmp = 0.0;  // compensated, as the partial sums
+    auto add = [](double& s, double& c, double x) {
+        const double u = s + x;
+        c += fabs(s) >= fabs(x) ? (s - u) + x : (x - u) + s;
+        s = u;
+    };
+    if (mode != 2)
+        for (int i = t; i < P0_PARTS; i += BLOCK) {
+            cmp += part[2 * i + 1];
+            add(acc, cmp, part[2 * i]);
+        }
+    sh[t] = acc;
+    shc[t] = cmp;
+    __syncthreads();
+    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            double s = sh[t], c = shc[t] + shc[t + o];
+            add(s, c, sh[t + o]);
+            sh[t] = s;
+            shc[t] = c;
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        P0State q = *st;
+        const double S = sh[0] + shc[0];
+        if (mode == 0) {
+            q.S0 = S;
+            q.p = q.p_prev = 1.0;
+        } else if (mode == 1) {
+            q.p_prev = q.p;
+            q.p = q.S0 / S;
+        }
+        *st = q;
+        const double dp = q.p - q.p_prev, rr = q.rho_ref0 * q.p, dt = q.P0_in * dp, dl = dp / q.p;
+        pd->rho_ref = rr;
+        pd->dp0_term = dt;
+        pd->dlnp0 = dl;
+        pf->rho_ref = (float)rr;
+        pf->dp0_term = (float)dt;
+        pf->dlnp0 = (float)dl;
     }
 }
 
@@ -306,6 +360,29 @@ Par<R> build_par(const lbfd_ctx* c) {
 
 bool ready_for_tables(const lbfd_ctx* c) { return c->have_params && (c->ns == 0 || c->have_mech); }
 
+// Closed domain: the sum of M / T over the current state and the P0 update
+// (mode as in p0_update_kernel), on the context's stream.
+lbfd_status launch_p0(lbfd_ctx* c, int mode) {
+    hipError_t e = hipSuccess;
+    double* part = dptr<double>(c, c->L.p0part);
+    if (mode != 2) {
+        const int N = (int)c->N;
+        if (c->fp32)
+            e = launch_p0_sum_f32(dptr<float>(c, c->cur ? c->L.T1 : c->L.T0),
+                                  dptr<float>(c, c->cur ? c->L.Y1 : c->L.Y0), N, c->ns,
+                                  dptr<Par<float>>(c, c->L.parf), part, c->stream);
+        else
+            e = launch_p0_sum_f64(dptr<double>(c, c->cur ? c->L.T1 : c->L.T0),
+                                  dptr<double>(c, c->cur ? c->L.Y1 : c->L.Y0), N, c->ns,
+                                  dptr<Par<double>>(c, c->L.pard), part, c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "P0 sum");
+    }
+    hipLaunchKernelGGL(p0_update_kernel, dim3(1), dim3(BLOCK), 0, c->stream, part,
+                       dptr<P0State>(c, c->L.p0), dptr<Par<float>>(c, c->L.parf),
+                       dptr<Par<double>>(c, c->L.pard), mode);
+    return hip_check(c, hipGetLastError(), "P0 update");
+}
+
 lbfd_status upload_tables(lbfd_ctx* c) {
     if (!ready_for_tables(c)) return LBFD_OK;
     Par<double> pd = build_par<double>(c);
@@ -318,6 +395,8 @@ lbfd_status upload_tables(lbfd_ctx* c) {
                                      hipMemcpyHostToDevice, c->stream),
                    "upload parameters");
     if (st) return st;
+    // a closed domain keeps its P0 across new parameters
+    if (c->params.closed && c->have_state && (st = launch_p0(c, 2))) return st;
     return hip_check(c, hipStreamSynchronize(c->stream), "upload parameters");
 }
 
@@ -661,6 +740,17 @@ lbfd_status lbfd_set_params(lbfd_ctx* c, const lbfd_params* p) {
     for (int f = 0; f < 6; ++f)
         if (c->grid.fd_bc[f] == LBFD_FD_DIRICHLET && !pos(p->fd_face[f][0]))
             return fail(c, LBFD_E_INVAL, "Dirichlet face temperature must be positive");
+    if (p->closed != 0 && p->closed != 1) return fail(c, LBFD_E_INVAL, "closed must be 0 or 1");
+    if (p->closed) {
+        for (int f = 0; f < 6; ++f)
+            if (c->grid.lb_bc[f] == LBFD_LB_VELOCITY_INLET ||
+                c->grid.lb_bc[f] == LBFD_LB_PRESSURE_OUTLET)
+                return fail(c, LBFD_E_INVAL, "a closed domain has no inlet or outlet face");
+        if (!(p->r_gas >= 0.0) || !(p->r_gas < p->cp))
+            return fail(c, LBFD_E_INVAL, "closed domain: 0 <= r_gas < cp");
+    }
+    if (c->have_state && c->have_params && p->closed != c->params.closed)
+        return fail(c, LBFD_E_STATE, "closing or opening the domain needs a new init_state");
     lbfd_status st = set_device(c);
     if (st) return st;
     lbfd_params old = c->params;
@@ -719,6 +809,19 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
     c->cur = 0;
     c->odd = 0;
     c->steps = 0;
+    if (c->params.closed) {  // P0 = P0_in for the initial state; its sum of M / T
+        const Par<double> pd = build_par<double>(c);
+        P0State q{};
+        q.p = q.p_prev = 1.0;
+        q.rho_ref0 = pd.rho_ref;
+        q.P0_in = pd.rho_ref * c->params.r_gas;
+        st = hip_check(c, hipMemcpyAsync(dptr<char>(c, c->L.p0), &q, sizeof(q),
+                                         hipMemcpyHostToDevice, c->stream),
+                       "closed-domain state");
+        if (st) return st;
+        if ((st = launch_p0(c, 0))) return st;
+        if ((st = hip_check(c, hipStreamSynchronize(c->stream), "closed-domain state"))) return st;
+    }
     c->have_state = true;
     return LBFD_OK;
 }
@@ -745,6 +848,7 @@ lbfd_status lbfd_step_phase(lbfd_ctx* c, int32_t n, int32_t phase) {
         c->cur ^= 1;
         if (phase & PH_LB) c->odd ^= 1;
         c->steps++;
+        if (c->params.closed && (st = launch_p0(c, 1))) return st;  // P0 of the new state
     }
     return LBFD_OK;
 }
@@ -844,6 +948,16 @@ lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
     out->n_flagged_fp64 = (int64_t)h[DG_FLAG];
     out->n_fallback = (int64_t)h[DG_FALLBACK];
     for (int b = 0; b < 4; ++b) out->n_fallback_reason[b] = (int64_t)h[DG_FB_REASON + b];
+    out->p0_ratio = 1.0;
+    if (c->params.closed) {
+        P0State q;
+        st = hip_check(c, hipMemcpyAsync(&q, dptr<char>(c, c->L.p0), sizeof(q),
+                                         hipMemcpyDeviceToHost, c->stream),
+                       "closed-domain state");
+        if (st) return st;
+        if ((st = hip_check(c, hipStreamSynchronize(c->stream), "closed-domain state"))) return st;
+        out->p0_ratio = q.p;
+    }
     out->step = c->steps;
     if (out->n_nonfinite > 0) return fail(c, LBFD_E_NUMERIC, "non-finite values in the state");
     return LBFD_OK;

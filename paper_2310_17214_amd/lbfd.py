@@ -58,7 +58,8 @@ class Params(C.Structure):
                 ("body_force", C.c_double * 3), ("Y_in", C.c_double * MAX_SPECIES),
                 ("Le", C.c_double * MAX_SPECIES),
                 ("fd_face", (C.c_double * (1 + MAX_SPECIES)) * 6),
-                ("n_sub", C.c_int32), ("ign_threshold", C.c_double)]
+                ("n_sub", C.c_int32), ("ign_threshold", C.c_double),
+                ("closed", C.c_int32), ("r_gas", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -78,7 +79,7 @@ class Diag(C.Structure):
                 ("Tmin", C.c_double), ("Tmax", C.c_double), ("n_nonfinite", C.c_int64),
                 ("n_tau_bad", C.c_int64), ("n_negY", C.c_int64), ("n_flagged_fp64", C.c_int64),
                 ("n_fallback", C.c_int64), ("step", C.c_int64),
-                ("n_fallback_reason", C.c_int64 * 4)]
+                ("n_fallback_reason", C.c_int64 * 4), ("p0_ratio", C.c_double)]
 
 
 _lib = None
@@ -167,6 +168,7 @@ def make_params(s: dict) -> Params:
         for j, v in enumerate(s["fd_val"][f]):
             p.fd_face[f][j] = v
     p.n_sub, p.ign_threshold = s["n_sub"], s["theta_ign"]
+    p.closed, p.r_gas = int(s.get("closed", 0)), float(s.get("r_gas", 0.0))
     return p
 
 

@@ -154,6 +154,82 @@ def test_bed_crop_fp32_1000_steps():
     assert ctx.diagnostics()["n_flagged_fp64"] > 0
 
 
+def _close(s):
+    """The same setup as a closed domain (Sec. 3.1): walls where the inlet and
+    outlet were, and P0(t) from the fixed mass, with r = 0.3 cp."""
+    s = dict(s)
+    s["lb_bc"] = ["wall" if b in ("inlet", "outlet") else b for b in s["lb_bc"]]
+    s["u_in"] = [0.0, 0.0, 0.0]
+    s["closed"], s["r_gas"] = 1, 0.3 * s["cp"]
+    return s
+
+
+def test_closed_bed_crop_fp64():
+    """The bed crop as a closed domain (walls for the inlet and outlet, the
+    fresh-gas Dirichlet face kept, the one-step flame): the GPU's P0 ratio and
+    fields follow the oracle's within 1e-12 after 300 steps, and the domain's
+    mass stays fixed."""
+    wl = _crop("fp64")
+    s = _close(wl.setup)
+    say("closed bed crop fp64, 300 steps")
+    ctx, orc = run_both(s, wl.phi, wl.T0, wl.Y0, 300)
+    p_gpu, p_orc = ctx.diagnostics()["p0_ratio"], orc.p0()
+    say(p_gpu, p_orc)
+    assert abs(p_orc - 1.0) > 1e-3  # the test exercises a moving P0
+    assert abs(p_gpu - p_orc) <= 1e-12 * p_orc
+    errs = compare(ctx, orc)
+    say(errs)
+    assert max(errs.values()) <= 1e-12, errs
+    rho = ctx.fields()["rho"]
+    fresh = lb().Context(s, wl.phi)
+    fresh.init_state(wl.T0, wl.Y0)
+    m0 = fresh.fields()["rho"].sum()
+    assert abs(rho.sum() - m0) <= 1e-12 * m0
+
+
+def test_closed_bed_crop_fp32_1000_steps():
+    """The bed crop as a closed domain in FP32 (FP64 island cells included)
+    against the FP64 oracle after 1000 steps: the FP32 bars, and P0 within
+    1e-5."""
+    wl64, wl32 = _crop("fp64"), _crop("fp32")
+    s64, s32 = _close(wl64.setup), _close(wl32.setup)
+    say("closed bed crop fp32 vs oracle, 1000 steps")
+    ctx = lb().Context(s32, wl32.phi)
+    ctx.init_state(wl32.T0, wl32.Y0)
+    ctx.step(1000)
+    orc = O.Oracle(s64, wl64.phi)
+    orc.init_state(wl64.T0, wl64.Y0)
+    orc.step(1000)
+    d = ctx.diagnostics()
+    say(d["p0_ratio"], orc.p0())
+    assert abs(orc.p0() - 1.0) > 1e-3
+    assert abs(d["p0_ratio"] - orc.p0()) <= 1e-5 * orc.p0()
+    errs = compare(ctx, orc)
+    say(errs)
+    for k, e in errs.items():
+        if k == "T" or k.startswith("Y"):
+            assert e <= 1e-4, (k, e)
+    # The FP32 error of u is absolute (a difference of populations of size
+    # rho cs^2), not relative to the flow: the open crop's bar, 1e-5 of its
+    # max |u| (0.0225), in velocity units.  The closed crop's flow comes from
+    # the thermal expansion alone (max |u| 0.0018), so the same rounding is a
+    # larger fraction of it.
+    ug, uo = ctx.fields()["u"], orc.fields()["u"]
+    say("max |u|", np.abs(uo).max(), "max |du|", np.abs(ug - uo).max())
+    assert np.abs(ug - uo).max() <= 1e-5 * 0.0225
+    assert d["n_flagged_fp64"] > 0
+
+
+def test_closing_an_open_run_is_rejected():
+    s, phi, T0, Y0, u0 = small_box()
+    ctx = lb().Context(s, phi)
+    ctx.init_state(T0, Y0, u0)
+    closed = _close(s)
+    closed["lb_bc"] = s["lb_bc"]  # the grid keeps its inlet and outlet
+    with pytest.raises(Exception):
+        ctx.set_params(closed)
+
+
 @pytest.mark.parametrize("mask", [1, 2, 3, 6])
 def test_phase_hooks(mask):
     s, phi, T0, Y0, u0 = small_box()
