@@ -59,6 +59,17 @@ def make_workload(name):
         return W.bed_sphere_9sp(precision="fp32")
     if name == "superquadric_bed":
         return W.bed_superquadric_9sp(precision="fp32")
+    if name == "sphere_bed_closed":
+        # the one-step sphere bed as a closed box: walls where the inlet and
+        # outlet were, P0(t) from the fixed mass, r = cp (gamma - 1) / gamma
+        # with gamma = 1.4
+        wl = W.bed_one_step(precision="fp32")
+        s = wl.setup
+        s["lb_bc"] = ["wall" if b in ("inlet", "outlet") else b for b in s["lb_bc"]]
+        s["u_in"] = [0.0, 0.0, 0.0]
+        s["closed"], s["r_gas"] = 1, s["cp"] * 0.4 / 1.4
+        wl.name = wl.name.replace("sphere_bed", "sphere_bed_closed")
+        return wl
     if name == "elongated_bed_slab":
         # one GPU's share (third of eight 128-cell slabs, with a halo plane
         # on each side) of the 1024x256x256 elongated bed
