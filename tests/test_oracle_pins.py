@@ -370,6 +370,44 @@ def test_P18_closed_box_constant_volume_flame_temperature():
     assert o2.p0() == 1.0
 
 
+def test_P19_closed_box_p0_is_the_mass_ratio_of_the_state():
+    """Closed, non-uniform, flowing, reacting box: after every step P0 / P0_in
+    equals sum(M/T) of the initial state over sum(M/T) of the current one
+    (recomputed here from the read-back fields with the molar masses), and the
+    domain's mass stays fixed (Sec. 3.1)."""
+    mech = W.mech_one_step(A=W.one_step_rate_constant(tau_steps=20.0))
+    s = W.base_setup(3, 9, 8, 7, 4)
+    s["mech"], s["Y_in"] = mech, W.ONE_STEP_Y_IN
+    s["lb_bc"] = ["wall", "wall", "periodic", "periodic", "wall", "wall"]
+    s["fd_bc"] = ["neumann", "dirichlet", "periodic", "periodic", "neumann", "neumann"]
+    s["fd_val"][1] = [900.0] + W.ONE_STEP_Y_BURNT
+    s["F_b"] = [2e-5, 0.0, 0.0]
+    s["closed"], s["r_gas"] = 1, 0.25 * s["cp"]
+    shape = (7, 8, 9)
+    rng = np.random.default_rng(3)
+    phi = np.clip(rng.uniform(-0.5, 1.2, shape), 0.0, 1.0)
+    T0 = rng.uniform(400.0, 1000.0, shape)
+    Y0 = np.array(W.ONE_STEP_Y_IN)[:, None, None, None] * np.ones((4,) + shape)
+    o = O.Oracle(s, phi)
+    o.init_state(T0, Y0)
+    M = np.array(mech["M"])
+
+    def sum_m_over_t():
+        Y = np.stack([o.read(O.F_Y, k) for k in range(4)])
+        mbar = 1.0 / np.tensordot(1.0 / M, Y, axes=1)
+        return np.sum(mbar / o.read(O.F_T))
+
+    S0, m0 = sum_m_over_t(), o.read(O.F_RHO).sum()
+    moved = 0.0
+    for _ in range(40):
+        o.step(1)
+        p = o.p0()
+        assert abs(p - S0 / sum_m_over_t()) <= 1e-13 * p
+        assert abs(o.read(O.F_RHO).sum() - m0) <= 1e-13 * m0
+        moved = max(moved, abs(p - 1.0))
+    assert moved > 1e-3
+
+
 def test_P11_reaction_enthalpy_per_substep():
     """Every explicit sub-step conserves cp T + sum_k dh_f,k Y_k (Eq. 9)
     and the total mass fraction (element-balanced reactions, Eq. 8)."""
