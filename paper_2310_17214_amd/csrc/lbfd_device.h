@@ -334,7 +334,7 @@ struct P0State {
     double rho_ref0;       // rho_ref at p = 1
     double P0_in;          // rho_ref0 * r_gas
 };
-constexpr int P0_PARTS = 1024;  // workgroups (and partial sums) of the P0 sum
+constexpr int P0_PARTS = 4096;  // workgroups (and partial sums) of the P0 sum
 
 template <typename R>
 struct StepArgs {
