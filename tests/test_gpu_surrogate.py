@@ -153,6 +153,34 @@ def test_s4_forced_fallback_equals_the_exact_path_bitwise():
     assert d["mass"] == pytest.approx(dr["mass"], rel=1e-13)
 
 
+def test_s4_forced_fallback_in_a_closed_domain_equals_the_exact_path_bitwise():
+    """Closed domain (P0(t), Sec. 3.1) with the surrogate installed and every
+    cell falling back: the same bits as the exact FP64 reaction path, and the
+    same P0 ratio (the surrogate and fallback kernels read the P0-scaled EOS;
+    the dP0/dt terms live in the transport step)."""
+    wl = _crop9()
+    s = dict(wl.setup)
+    s["lb_bc"] = ["wall" if b in ("inlet", "outlet") else b for b in s["lb_bc"]]
+    s["u_in"] = [0.0, 0.0, 0.0]
+    s["closed"], s["r_gas"] = 1, 0.3 * s["cp"]
+    wl.setup = s
+    ns = s["ns"]
+    T, Y = _random_states(200, ns, 2)
+    w, norm = _model(ns, T, Y, 9)
+    norm = dict(norm, lo=norm["lo"] + 1e4, hi=norm["hi"] + 1e4)  # nothing inside the envelope
+    say("S4 forced fallback, closed domain, 5 steps")
+    ctx = lb().Context(s, wl.phi)
+    _install(ctx, w, norm)
+    ctx.init_state(wl.T0, wl.Y0)
+    ctx.step(5)
+    ref = _exact_all_fp64(wl, 5)
+    a, b = ctx.fields(), ref.fields()
+    for k in ("T", "Y", "u", "divu"):
+        assert np.array_equal(a[k], b[k]), k
+    pa, pb = ctx.diagnostics()["p0_ratio"], ref.diagnostics()["p0_ratio"]
+    assert pa == pb and pa != 1.0
+
+
 def test_s4_fallback_cells_equal_the_exact_path_in_a_mixed_step():
     import torch
 
