@@ -114,7 +114,11 @@ typedef struct {
                                         change over the previous step enters the
                                         temperature equation (Eq. energy-transport-
                                         DI-version) and the thermal divergence.  No
-                                        inlet or outlet face.  0: P0 fixed           */
+                                        inlet or outlet face.  init_state starts P0 at
+                                        P0_in with the mass of the state it is given,
+                                        so a restore through init_state and
+                                        set_populations restarts P0 there.  0: P0
+                                        fixed                                        */
     double r_gas;                    /* closed domain: R / M_ref in the units of cp,
                                         0 <= r_gas < cp                              */
 } lbfd_params;
