@@ -115,10 +115,9 @@ typedef struct {
                                         temperature equation (Eq. energy-transport-
                                         DI-version) and the thermal divergence.  No
                                         inlet or outlet face.  init_state starts P0 at
-                                        P0_in with the mass of the state it is given,
-                                        so a restore through init_state and
-                                        set_populations restarts P0 there.  0: P0
-                                        fixed                                        */
+                                        P0_in with the mass of the state it is given;
+                                        a checkpoint restore also sets the P0 state
+                                        (lbfd_set_p0_state).  0: P0 fixed             */
     double r_gas;                    /* closed domain: R / M_ref in the units of cp,
                                         0 <= r_gas < cp                              */
 } lbfd_params;
@@ -196,6 +195,16 @@ lbfd_status lbfd_init_state(lbfd_ctx* ctx, const double* T, const double* Y, con
  * thermal divergence (N doubles, may be NULL); together with lbfd_init_state
  * this restores a checkpoint written with lbfd_read. */
 lbfd_status lbfd_set_populations(lbfd_ctx* ctx, const double* g, const double* divu);
+
+/* Closed domain (Sec. 3.1): the thermodynamic-pressure state that a checkpoint
+ * needs besides the fields: out/in[3] = {S0, p, p_prev}, the sum of M/T over
+ * the cells of the initial state, P0/P0_in for the next step and for the last
+ * one (host arrays of 3 doubles).  lbfd_set_p0_state, after lbfd_init_state,
+ * restores it and rewrites the parameter blocks' EOS and dP0/dt terms.
+ * LBFD_E_STATE when the domain is not closed or no state is set; LBFD_E_INVAL
+ * for non-positive or non-finite values. */
+lbfd_status lbfd_get_p0_state(lbfd_ctx* ctx, double* out);
+lbfd_status lbfd_set_p0_state(lbfd_ctx* ctx, const double* in);
 
 /* Enqueue n coupled steps on the context's stream; returns without waiting. */
 lbfd_status lbfd_step(lbfd_ctx* ctx, int32_t n);

@@ -826,6 +826,50 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
     return LBFD_OK;
 }
 
+lbfd_status lbfd_get_p0_state(lbfd_ctx* c, double* out) {
+    if (!c || !out) return LBFD_E_INVAL;
+    if (!c->have_state || !c->params.closed)
+        return fail(c, LBFD_E_STATE, "no closed-domain state");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    P0State q;
+    st = hip_check(c, hipMemcpyAsync(&q, dptr<char>(c, c->L.p0), sizeof(q), hipMemcpyDeviceToHost,
+                                     c->stream),
+                   "closed-domain state");
+    if (st) return st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "closed-domain state"))) return st;
+    out[0] = q.S0;
+    out[1] = q.p;
+    out[2] = q.p_prev;
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_set_p0_state(lbfd_ctx* c, const double* in) {
+    if (!c || !in) return LBFD_E_INVAL;
+    if (!c->have_state || !c->params.closed)
+        return fail(c, LBFD_E_STATE, "no closed-domain state");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(in[i]) || !(in[i] > 0.0))
+            return fail(c, LBFD_E_INVAL, "closed-domain state must be positive");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    P0State q;
+    st = hip_check(c, hipMemcpyAsync(&q, dptr<char>(c, c->L.p0), sizeof(q), hipMemcpyDeviceToHost,
+                                     c->stream),
+                   "closed-domain state");
+    if (st) return st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "closed-domain state"))) return st;
+    q.S0 = in[0];
+    q.p = in[1];
+    q.p_prev = in[2];
+    st = hip_check(c, hipMemcpyAsync(dptr<char>(c, c->L.p0), &q, sizeof(q), hipMemcpyHostToDevice,
+                                     c->stream),
+                   "closed-domain state");
+    if (st) return st;
+    if ((st = launch_p0(c, 2))) return st;  // the parameter blocks follow the restored P0
+    return hip_check(c, hipStreamSynchronize(c->stream), "closed-domain state");
+}
+
 lbfd_status lbfd_set_populations(lbfd_ctx* c, const double* g, const double* divu) {
     if (!c || !g) return LBFD_E_INVAL;
     if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");

@@ -26,7 +26,8 @@ LB_BC = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
 FD_BC = {"periodic": 0, "dirichlet": 1, "neumann": 2}
 
 EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd_set_mechanism",
-            "lbfd_set_params", "lbfd_init_state", "lbfd_set_populations", "lbfd_step",
+            "lbfd_set_params", "lbfd_init_state", "lbfd_set_populations",
+            "lbfd_get_p0_state", "lbfd_set_p0_state", "lbfd_step",
             "lbfd_step_phase", "lbfd_read", "lbfd_diagnostics", "lbfd_synchronize",
             "lbfd_step_bytes_per_cell", "lbfd_set_timing", "lbfd_kernel_time",
             "lbfd_set_surrogate", "lbfd_surrogate_eval", "lbfd_sample_states",
@@ -100,6 +101,8 @@ def lib():
         L.lbfd_set_params.argtypes = [vp, C.POINTER(Params)]
         L.lbfd_init_state.argtypes = [vp, _dp, _dp, _dp]
         L.lbfd_set_populations.argtypes = [vp, _dp, _dp]
+        L.lbfd_get_p0_state.argtypes = [vp, _dp]
+        L.lbfd_set_p0_state.argtypes = [vp, _dp]
         L.lbfd_step.argtypes = [vp, C.c_int32]
         L.lbfd_step_phase.argtypes = [vp, C.c_int32, C.c_int32]
         L.lbfd_read.argtypes = [vp, C.c_int32, C.c_int32, _dp]
@@ -270,6 +273,16 @@ class Context:
         d = _f64(divu) if divu is not None else None
         self._check(lib().lbfd_set_populations(self._h, g.ctypes.data_as(_dp),
                                                None if d is None else d.ctypes.data_as(_dp)))
+
+    def p0_state(self):
+        """Closed domain: (S0, p, p_prev) for a checkpoint."""
+        out = np.zeros(3)
+        self._check(lib().lbfd_get_p0_state(self._h, out.ctypes.data_as(_dp)))
+        return out
+
+    def set_p0_state(self, st):
+        st = _f64(st)
+        self._check(lib().lbfd_set_p0_state(self._h, st.ctypes.data_as(_dp)))
 
     def step(self, n=1):
         self._check(lib().lbfd_step(self._h, int(n)))

@@ -260,6 +260,30 @@ def test_checkpoint_resume_is_bitwise():
             assert np.array_equal(got[k], ref[k]), (prec, k)
 
 
+def test_closed_checkpoint_resume_is_bitwise():
+    """A closed domain resumes bitwise when the P0 state (S0, p, p_prev)
+    travels with the fields and populations."""
+    for prec in ("fp64", "fp32"):
+        wl = _crop(prec)
+        s = _close(wl.setup)
+        say(f"closed checkpoint {prec}")
+        a = lb().Context(s, wl.phi)
+        a.init_state(wl.T0, wl.Y0)
+        a.step(7)
+        g, f, p0 = a.populations(), a.fields(), a.p0_state()
+        a.step(6)
+        ref, pref = a.fields(), a.p0_state()
+        b = lb().Context(s, wl.phi)
+        b.init_state(f["T"], f["Y"])
+        b.set_populations(g, f["divu"])
+        b.set_p0_state(p0)
+        b.step(6)
+        got = b.fields()
+        for k in ("T", "Y", "u", "Ph", "divu"):
+            assert np.array_equal(got[k], ref[k]), (prec, k)
+        assert np.array_equal(b.p0_state(), pref)
+
+
 def test_runs_are_deterministic():
     wl = _crop("fp32")
     say("determinism fp32 crop")
