@@ -59,6 +59,8 @@ struct Par {
     R A_u, A_T, inv_eta2, T_s, cp, inv_cp, inv_Pr, rho_in, T_in, mu_ref, S_T_in, S;
     R rho_ref;        // rho_in * T_in / Mbar_in  (EOS numerator), times P0 / P0_in
                       // in a closed domain (rewritten on the device after each step)
+    R p0;             // closed domain: P0 / P0_in of the step (1 otherwise); scales
+                      // the single-gas EOS (with species it is in rho_ref)
     R dp0_term;       // closed domain: P0_in (p^n - p^{n-1}), the dP0/dt of the step
     R dlnp0;          // closed domain: (p^n - p^{n-1}) / p^n
     R inv_T_in;       // 1 / T_in, rounded once on the host
@@ -125,7 +127,7 @@ template <> __device__ __forceinline__ double flog<double>(double x) { return lo
 template <typename R, int NSM>
 __device__ __forceinline__ R eos(const Par<R>& P, R T, const R* Y) {
     if constexpr (NSM == 0) {
-        return P.rho_in * dvd(P.T_in, T);
+        return P.p0 * (P.rho_in * dvd(P.T_in, T));
     } else {
         R im = R(0);
 #pragma unroll

@@ -170,9 +170,11 @@ __global__ void p0_update_kernel(const double* __restrict__ part, P0State* __res
         *st = q;
         const double dp = q.p - q.p_prev, rr = q.rho_ref0 * q.p, dt = q.P0_in * dp, dl = dp / q.p;
         pd->rho_ref = rr;
+        pd->p0 = q.p;
         pd->dp0_term = dt;
         pd->dlnp0 = dl;
         pf->rho_ref = (float)rr;
+        pf->p0 = (float)q.p;
         pf->dp0_term = (float)dt;
         pf->dlnp0 = (float)dl;
     }
@@ -256,6 +258,7 @@ Par<R> build_par(const lbfd_ctx* c) {
     P.rho_in = (R)p.rho_in;
     P.T_in = (R)p.T_in;
     P.inv_T_in = (R)(1.0 / p.T_in);
+    P.p0 = (R)1;  // a closed domain's P0 ratio is written on the device
     P.mu_ref = (R)(p.rho_in * p.nu_in);
     P.S = (R)p.sutherland_S;
     P.S_T_in = (R)(p.T_in + p.sutherland_S);

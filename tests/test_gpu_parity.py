@@ -187,6 +187,23 @@ def test_closed_bed_crop_fp64():
     assert abs(rho.sum() - m0) <= 1e-12 * m0
 
 
+def test_closed_cylinder_channel_fp64_no_species():
+    """D2Q9, no species (M = 1 in the P0 sum), the cylinder channel closed by
+    walls, heated through its wall: P0 and the fields follow the oracle
+    within 1e-12."""
+    wl = W.cylinder_channel()
+    s = _close(wl.setup)
+    say("closed cylinder channel fp64, 300 steps")
+    ctx, orc = run_both(s, wl.phi, wl.T0, None, 300)
+    p_gpu, p_orc = ctx.diagnostics()["p0_ratio"], orc.p0()
+    say(p_gpu, p_orc)
+    assert abs(p_orc - 1.0) > 1e-4
+    assert abs(p_gpu - p_orc) <= 1e-12 * p_orc
+    errs = compare(ctx, orc)
+    say(errs)
+    assert max(errs.values()) <= 1e-12, errs
+
+
 def test_closed_bed_crop_fp32_1000_steps():
     """The bed crop as a closed domain in FP32 (FP64 island cells included)
     against the FP64 oracle after 1000 steps: the FP32 bars, and P0 within
