@@ -237,6 +237,30 @@ def test_closed_bed_crop_fp32_1000_steps():
     assert d["n_flagged_fp64"] > 0
 
 
+def test_closed_domain_arguments_are_checked():
+    """A closed domain refuses an inlet or outlet face and r_gas outside
+    [0, cp); the P0 state calls refuse an open domain."""
+    s, phi, T0, Y0, u0 = small_box()
+    with_inlet = dict(s, closed=1, r_gas=0.3 * s["cp"])  # the grid keeps its inlet
+    with pytest.raises(Exception):
+        lb().Context(with_inlet, phi)
+    for r in (-0.1 * s["cp"], s["cp"], 2.0 * s["cp"]):
+        with pytest.raises(Exception):
+            lb().Context(dict(_close(s), r_gas=r), phi)
+    ctx = lb().Context(s, phi)
+    ctx.init_state(T0, Y0, u0)
+    with pytest.raises(Exception):
+        ctx.p0_state()
+    with pytest.raises(Exception):
+        ctx.set_p0_state([1.0, 1.0, 1.0])
+    assert ctx.diagnostics()["p0_ratio"] == 1.0
+    closed = lb().Context(_close(s), phi)
+    closed.init_state(T0, Y0, u0)
+    for bad in ([0.0, 1.0, 1.0], [1.0, float("nan"), 1.0], [1.0, 1.0, -1.0]):
+        with pytest.raises(Exception):
+            closed.set_p0_state(bad)
+
+
 def test_closing_an_open_run_is_rejected():
     s, phi, T0, Y0, u0 = small_box()
     ctx = lb().Context(s, phi)
