@@ -19,7 +19,6 @@ Functions:
   bf16_round            round-to-nearest-even to bfloat16 (values kept in float64)
   forward               the perceptron, optionally with the kernel's rounding points
   source                x -> (omega_hat, fallback flags) with all checks
-  apply                 the full per-cell surrogate reaction step (fallback cells exact)
   step_source           the exact target omega_bar from the oracle's reactor
   loss_and_grad         FP64 mean-square loss and its gradient (backpropagation)
   adam                  one Adam update (Kingma and Ba, 2015)
@@ -153,21 +152,6 @@ def source(w, norm, setup, T, Y, p=1.0, emulate=True):
     omega_T = -(omega * dhf).sum(1)
     neg = np.any(Yv + omega / rho[:, None] < POS_TOL, axis=1)
     return omega, omega_T, out_env | over | resid | neg, raw
-
-
-def apply(w, norm, setup, T, Y, p=1.0, emulate=True):
-    """Per-cell surrogate reaction step from (T*, Y*): returns
-    (T_new, Y_new, divu_chem, fallback).  Fallback cells take the exact
-    FP64 integration (the oracle's reactor); dt = 1."""
-    T = np.atleast_1d(np.asarray(T, np.float64))
-    Y = np.atleast_2d(np.asarray(Y, np.float64))
-    omega, omega_T, fb, _ = source(w, norm, setup, T, Y, p, emulate)
-    rho = np.array([O.eos(setup, t, y) for t, y in zip(T, Y)])
-    Tn = T + omega_T / (rho * setup["cp"])
-    Yn = Y + omega / rho[:, None]
-    for i in np.nonzero(fb)[0]:
-        Tn[i], Yn[i] = O.reactor(setup, T[i], Y[i], 1)
-    return Tn, Yn, (Tn - T) / T, fb
 
 
 def step_source(setup, T, Y):

@@ -642,3 +642,169 @@ def test_low_mach_expansion_through_heater():
     Tout, uout = f["T"][0, 0, -2], f["u"][0][0, 0, -2]
     assert Tout > 450.0
     assert abs(uout / 0.01 - Tout / 300.0) / (Tout / 300.0) < 0.02
+
+
+# ------------------------------------------- reductions against the fields
+
+def _eos_np(setup, T, Y):
+    """Ideal-gas density at fixed thermodynamic pressure (Sec. 3.1, Eq.
+    rho-in-terms-of-P0-and-T), written out here from the fields:
+    rho = rho_in (T_in / T)(Mbar / Mbar_in), 1/Mbar = sum_k Y_k / M_k."""
+    M = np.asarray(setup["mech"]["M"], float)
+    inv_m = np.tensordot(1.0 / M, Y, axes=1)
+    inv_m_in = float(np.sum(np.asarray(setup["Y_in"], float) / M))
+    return setup["rho_in"] * (setup["T_in"] / T) * (inv_m_in / inv_m)
+
+
+def test_reductions_equal_sums_recomputed_from_the_fields():
+    """The conservation diagnostics are the sums their definitions name,
+    taken over the state the oracle exposes: mass = sum rho, species =
+    sum rho Y_k, enthalpy = sum rho (cp T + sum_k dh_f,k Y_k) of the state
+    after the step; kinetic energy = sum rho |u|^2 / 2 and max |u| of the
+    velocity the step's collision used (the moments read before the step,
+    with the density of that state); T extrema of the new state.  A
+    non-uniform, flowing, reacting crop with unequal molar masses and nine
+    species, so that no term can vanish by symmetry."""
+    wl = W.bed_sphere_9sp(nx=20, ny=12, nz=10, precision="fp64", bed=(3, 17), x_split=10,
+                          steps=0)
+    s = wl.setup
+    s["cp"] = 1.3  # cp != 1, so that a dropped cp shows
+    o = O.Oracle(s, wl.phi)
+    o.init_state(wl.T0, wl.Y0)
+    o.step(7)
+    before = o.fields()
+    o.step(1)
+    after = o.fields()
+    d = o.diag()
+    T, Y = after["T"], after["Y"]
+    rho = _eos_np(s, T, Y)
+    dhf = np.asarray(s["mech"]["dhf"], float)
+    assert np.abs(rho - after["rho"]).max() <= 1e-14 * rho.max()
+    assert d[O.D_MASS] == pytest.approx(rho.sum(), rel=1e-13)
+    for k in range(9):
+        assert abs(d[O.D_SPECIES + k] - (rho * Y[k]).sum()) <= 1e-13 * rho.sum()
+    h = s["cp"] * T + np.tensordot(dhf, Y, axes=1)
+    assert d[O.D_ENTHALPY] == pytest.approx((rho * h).sum(), rel=1e-13)
+    uu = np.sum(before["u"] ** 2, axis=0)
+    assert uu.max() > 1e-8  # the crop flows
+    assert d[O.D_KINETIC] == pytest.approx(0.5 * (before["rho"] * uu).sum(), rel=1e-12)
+    assert d[O.D_UMAX] == pytest.approx(np.sqrt(uu.max()), rel=1e-13)
+    assert d[O.D_TMIN] == T.min() and d[O.D_TMAX] == T.max()
+    assert d[O.D_STEP] == 8
+
+
+# ------------------------------------------------ mass action with M_k != 1
+
+def _mass_action_setup(M, nu_f, nu_r, A, rev=0, lnKc_a=0.0, lnKc_b=0.0, n_sub=1,
+                       Y_in=None):
+    ns = len(M)
+    mech = dict(M=list(M), dhf=[0.0] * ns, mu_star=[1.0] * ns, nu_f=[nu_f], nu_r=[nu_r],
+                A=[A], beta=[0.0], theta=[0.0], rev=[rev], lnKc_a=[lnKc_a], lnKc_b=[lnKc_b])
+    return _reactor_setup(mech, Y_in or [1.0 / ns] * ns, n_sub=n_sub)
+
+
+def test_second_order_decay_with_unequal_molar_masses():
+    """2A -> B (M_A = 3, M_B = 6, inert D with M_D = 11), no heat release:
+    with [A] = rho Y_A / M_A and omega_A = -2 M_A k [A]^2 (Eq. 8), each
+    explicit sub-step is Y_A <- Y_A - 2 h k rho Y_A^2 / M_A and
+    Y_B <- Y_B + 2 h k rho Y_A^2 / M_A, rho from the EOS of the sub-step's
+    state.  The recurrence is run here from the definitions; a dropped or
+    mixture-averaged molar mass in the concentration changes it."""
+    M = [3.0, 6.0, 11.0]
+    k = 0.8
+    s = _mass_action_setup(M, [2, 0, 0], [0, 1, 0], k, n_sub=3, Y_in=[0.2, 0.1, 0.7])
+    T, Y = 950.0, np.array([0.45, 0.15, 0.40])
+    h = 1.0 / 3
+    ref = Y.copy()
+    for n in range(1, 31):
+        for _ in range(3):
+            rho = _eos_np(s, T, ref[:, None])[0]
+            q = k * (rho * ref[0] / M[0]) ** 2
+            ref = ref + h * np.array([-2.0 * M[0] * q, M[1] * q, 0.0]) / rho
+        if n in (1, 5, 30):
+            T1, Y1 = O.reactor(s, T, Y, n)
+            assert T1 == T
+            assert np.abs(Y1 - ref).max() <= 1e-14, (n, Y1, ref)
+    assert ref[0] < 0.3  # A has been consumed noticeably
+
+
+def test_bimolecular_equilibrium_with_unequal_molar_masses_is_a_fixed_point():
+    """A + B = C (M_A = 2, M_B = 5, M_C = 7) plus an inert diluent, started
+    where the law of mass action balances, [C] / ([A][B]) = K_c with
+    [X_k] = rho Y_k / M_k and rho from the EOS of that composition: forward
+    and reverse rates of progress cancel and nothing moves.  The equilibrium
+    composition is solved here; with 1/Mbar or no 1/M_k in the
+    concentrations the balance would lie elsewhere."""
+    from scipy.optimize import brentq
+
+    M = [2.0, 5.0, 7.0, 4.0]
+    a, b = 1.1, 900.0
+    s = _mass_action_setup(M, [1, 1, 0, 0], [0, 0, 1, 0], 2.0, rev=1, lnKc_a=a, lnKc_b=b,
+                           n_sub=2, Y_in=[0.1, 0.2, 0.1, 0.6])
+    T = 800.0
+    Kc = math.exp(a + b / T)
+    YA, YB = 0.08, 0.15
+
+    def resid(YC):
+        Y = np.array([YA, YB, YC, 1.0 - YA - YB - YC])
+        rho = _eos_np(s, T, Y[:, None])[0]
+        return rho * YC / M[2] - Kc * (rho * YA / M[0]) * (rho * YB / M[1])
+
+    YC = brentq(resid, 1e-12, 1.0 - YA - YB - 1e-6, xtol=1e-16, rtol=1e-15)
+    Y0 = np.array([YA, YB, YC, 1.0 - YA - YB - YC])
+    assert 1e-3 < YC < 0.7
+    T1, Y1 = O.reactor(s, T, Y0, 25)
+    assert T1 == T
+    assert np.abs(Y1 - Y0).max() <= 1e-13
+    # a composition off the balance moves toward it
+    Yoff = np.array([YA, YB, 0.5 * YC, 1.0 - YA - YB - 0.5 * YC])
+    _, Y2 = O.reactor(s, T, Yoff, 3)
+    assert Y2[2] > Yoff[2]
+
+
+# ------------------------------------------------------- upwind advection
+
+def test_first_order_upwind_on_a_quadratic_field():
+    """Advection alone (no diffusion: nu = 0 makes mu, lambda and rho D zero;
+    no heat exchange, no chemistry) of a field quadratic along every axis by
+    the initial uniform velocity with mixed signs: first-order upwind
+    differences (Sec. 3.3, FD convection) give, at every interior cell,
+    T* = T - sum_a u_a (T(x) - T(x - s_a e_a)) s_a with s_a the sign of u_a:
+    for q = c x^2 the upwind difference is c (2x - 1) for u > 0 and
+    c (2x + 1) for u < 0, unlike central (2cx) or downwind ones.  The same
+    holds for a mass fraction."""
+    n = (9, 8, 7)  # nx, ny, nz
+    s = W.base_setup(3, n[0], n[1], n[2], 2)
+    s["nu_in"] = 0.0
+    s["A_T"] = 0.0
+    s["mech"]["M"] = [1.0, 2.0]
+    s["Y_in"] = [0.5, 0.5]
+    s["lb_bc"] = ["wall"] * 6
+    s["fd_bc"] = ["neumann"] * 6
+    shape = (n[2], n[1], n[0])
+    z, y, x = np.meshgrid(*[np.arange(m, dtype=float) for m in shape], indexing="ij")
+    cT = (0.5, -0.75, 0.25)   # per axis x, y, z
+    cY = (1e-3, 2e-3, -1.5e-3)
+    T0 = 600.0 + cT[0] * x ** 2 + cT[1] * y ** 2 + cT[2] * z ** 2
+    Y0a = 0.4 + cY[0] * x ** 2 + cY[1] * y ** 2 + cY[2] * z ** 2
+    Y0 = np.stack([Y0a, 1.0 - Y0a])
+    u = np.array([0.013, -0.021, 0.017])
+    u0 = u[:, None, None, None] * np.ones((3,) + shape)
+    o = O.Oracle(s, np.zeros(shape))
+    o.init_state(T0, Y0, u0)
+    o.step(1)
+    T1, Y1 = o.read(O.F_T), o.read(O.F_Y, 0)
+
+    def upwind(c, u):
+        d = np.zeros(shape)
+        for a, q in enumerate((x, y, z)):
+            d += u[a] * c[a] * (2.0 * q - 1.0 if u[a] > 0 else 2.0 * q + 1.0)
+        return d
+
+    inner = (slice(1, -1),) * 3
+    refT = (T0 - upwind(cT, u))[inner]
+    refY = (Y0a - upwind(cY, u))[inner]
+    assert np.abs(T1[inner] - refT).max() <= 1e-12 * 700.0
+    assert np.abs(Y1[inner] - refY).max() <= 1e-14
+    # the step did advect (not a trivial fixed point)
+    assert np.abs(T1[inner] - T0[inner]).min() > 1e-4
