@@ -101,24 +101,23 @@ def halo_measure(ctx, stream, reps=50):
     packed bytes."""
     import torch
 
-    nx = ctx.shape[2]
     nb = ctx.halo_bytes()
     elem = 4 if ctx.precision == "fp32" else 8
     dt = torch.float32 if elem == 4 else torch.float64
     bufs = [torch.empty(nb // elem, dtype=dt, device="cuda") for _ in range(2)]
-    faces = ((nx - 2, 1, 0, 1), (1, -1, nx - 1, -1))  # (pack x, dir, unpack x, dir)
+    faces = (-1, 1)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     for _ in range(3):
-        for (xp, d, _, _), b in zip(faces, bufs):
-            ctx.halo_pack(xp, d, b)
+        for f, b in zip(faces, bufs):
+            ctx.halo_pack(f, b)
     ev[0].record(stream)
     for _ in range(reps):
-        for (xp, d, _, _), b in zip(faces, bufs):
-            ctx.halo_pack(xp, d, b)
+        for f, b in zip(faces, bufs):
+            ctx.halo_pack(f, b)
     ev[1].record(stream)
     for _ in range(reps):
-        for (_, _, xu, d), b in zip(faces, bufs):
-            ctx.halo_unpack(xu, d, b)
+        for f, b in zip(faces, bufs):
+            ctx.halo_unpack(f, b)
     ev[2].record(stream)
     ctx.synchronize()
     pack_us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
@@ -133,16 +132,18 @@ def halo_measure(ctx, stream, reps=50):
             "note": "halo copies only; the transfers between GPUs are not run"}
 
 
-def cpu_baseline(wl, target_s=15.0):
+def cpu_baseline(wl, target_s=15.0, one_thread_s=8.0):
     """The FP64 CPU oracle, as it stands, on a bounded sample of the same
     workload: whole-grid steps from the initial state, as many as fit in about
-    `target_s` seconds (at least two)."""
+    `target_s` seconds (at least two) on every host thread, then about
+    `one_thread_s` seconds of the following steps on one thread."""
     from oracle import oracle as O
 
     wl64 = dict(wl.setup)
     wl64["precision"] = "fp64"
     orc = O.Oracle(wl64, wl.phi)
     orc.init_state(wl.T0, wl.Y0 if wl.setup["ns"] else None)
+    threads = O.nthreads()
     t0 = time.perf_counter()
     orc.step(1)
     first = time.perf_counter() - t0
@@ -150,10 +151,21 @@ def cpu_baseline(wl, target_s=15.0):
     orc.step(more)
     dt = time.perf_counter() - t0
     steps = 1 + more
-    return {"value": round(wl.cells * steps / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": O.nthreads(), "kind": "oracle",
-            "sample": f"{steps} steps of the full {wl.setup['nx']}x{wl.setup['ny']}x"
-                      f"{wl.setup['nz']} grid from the initial state, {dt:.1f} s"}
+    mlups = wl.cells * steps / dt / 1e6
+    # one thread: as many steps as the all-thread rate says fit
+    O.set_threads(1)
+    n1 = max(1, int(one_thread_s * mlups / threads * 1e6 / wl.cells))
+    t1 = time.perf_counter()
+    orc.step(n1)
+    dt1 = time.perf_counter() - t1
+    O.set_threads(threads)
+    grid = f"{wl.setup['nx']}x{wl.setup['ny']}x{wl.setup['nz']}"
+    return {"value": round(mlups, 3), "unit": "MLUPS",
+            "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{steps} steps of the full {grid} grid from the initial state, "
+                      f"{dt:.1f} s on {threads} threads",
+            "one_thread": {"value": round(wl.cells * n1 / dt1 / 1e6, 3), "unit": "MLUPS",
+                           "cores": 1, "sample": f"the next {n1} steps, {dt1:.1f} s"}}
 
 
 MLP_FLOP_PER_CELL = 2 * (11 * 256 + 256 * 256 + 256 * 9)   # 141,312 (9 species)
@@ -305,16 +317,127 @@ def copy_probe():
                       b.numel() * 4}))
 
 
+def survey_bytes_per_cell(setup):
+    """Algorithmic bytes per cell and step of the method, each array moved
+    once: the LB part reads and writes the Q populations in place and reads
+    rho, T, phi_s and divu and writes u; the FD + chemistry part reads T, Y_k,
+    u and phi_s and writes T, Y_k, rho and divu: s (2Q + 4 + d) + s (5 + 2 ns
+    + d) with s the storage size (244 B for D3Q19, FP32, 4 species; 284 B
+    with 9; 248 B for D2Q9 in FP64 without species)."""
+    d = setup["dim"]
+    Q = 9 if d == 2 else 19
+    s = 4 if setup.get("precision", "fp64") == "fp32" else 8
+    return float(s * ((2 * Q + 4 + d) + (5 + 2 * setup["ns"] + d)))
+
+
+def measure(wl, steps, warmup, settle_ms, stream=None, timing=True):
+    """MLUPS of `steps` coupled steps after `warmup` untimed steps (HIP events
+    on the context's stream), then the same number of steps again with every
+    kernel launch timed, for the kernels' own mean durations.  Before the
+    warm-up the context steps for `settle_ms` of wall time (untimed) so that
+    the GPU's clocks have ramped up as in a long run."""
+    import torch
+
+    from paper_2310_17214_amd import lbfd
+
+    ctx = lbfd.Context(wl.setup, wl.phi, stream=stream)
+    ctx.init_state(wl.T0, wl.Y0 if wl.setup["ns"] else None)
+    settle = 0
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < settle_ms:
+        ctx.step(10)
+        ctx.synchronize()
+        settle += 10
+    ctx.step(warmup)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(ctx.stream)
+    ctx.step(steps)
+    e1.record(ctx.stream)
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    diag = ctx.diagnostics()
+    out = {"ctx": ctx, "ms": ms, "ms_step": ms / steps, "wall": wall, "settle": settle,
+           "mlups": wl.cells * steps / (ms * 1e-3) / 1e6, "diag": diag}
+    if timing:
+        ctx.set_timing(True)
+        ctx.step(steps)
+        out["step_kernel"] = ctx.kernel_time(lbfd.LBFD_KERNEL_STEP)
+        out["island_kernel"] = ctx.kernel_time(lbfd.LBFD_KERNEL_ISLAND)
+        ctx.set_timing(False)
+    return out
+
+
+def roofline(wl, m, traffic=None):
+    """The step kernel against the HBM roofline: achieved = the method's
+    algorithmic bytes per cell (survey_bytes_per_cell) x cells / the kernel's
+    mean launch duration; the kernel's own count of what it moves beside it."""
+    bpc = survey_bytes_per_cell(wl.setup)
+    kbpc = m["ctx"].bytes_per_cell()
+    n, kms = m["step_kernel"]
+    achieved = bpc * wl.cells / (kms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "bytes_per_cell": bpc, "bytes_per_launch": bpc * wl.cells,
+            "bytes_per_cell_kernel": kbpc,
+            "frac_kernel_bytes": round(kbpc * wl.cells / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel": "step_kernel (fused LB+FD+chemistry+partials)",
+            "kernel_ms": round(kms, 5), "kernel_launches": n,
+            "island_ms": round(m["island_kernel"][1], 5), "island_launches": m["island_kernel"][0]}
+
+
+def config_line(name, steps, warmup, settle_ms, log):
+    """One more workload of the method at its own size: MLUPS and the step
+    kernel's roofline."""
+    import torch
+
+    t0 = time.perf_counter()
+    wl = make_workload(name)
+    gen = time.perf_counter() - t0
+    log(f"config {wl.name}: {wl.cells} cells (inputs built in {gen:.1f} s)")
+    m = measure(wl, steps, warmup, settle_ms)
+    line = {"workload": wl.name, "cells": wl.cells,
+            "lattice": "D2Q9" if wl.setup["dim"] == 2 else "D3Q19",
+            "species": wl.setup["ns"], "reactions": len(wl.setup["mech"]["A"]),
+            "precision": wl.setup.get("precision", "fp64"),
+            "value": round(m["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(m["ms_step"], 5),
+            "steps": steps, "warmup": warmup, "settle_steps": m["settle"],
+            "roofline": roofline(wl, m),
+            "diagnostics": {"Tmax": m["diag"]["Tmax"], "umax": m["diag"]["umax"],
+                            "n_flagged_fp64": m["diag"]["n_flagged_fp64"],
+                            "n_nonfinite": m["diag"]["n_nonfinite"]}}
+    del m
+    torch.cuda.empty_cache()
+    return line
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--settle-ms", type=float, default=300.0)
     ap.add_argument("--workload", default="sphere_bed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--mlp-probe", type=int, default=0, metavar="STEPS")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -331,51 +454,24 @@ def main():
 
     import torch
 
-    from paper_2310_17214_amd import lbfd
-
-    print(f"bench: building workload {args.workload}", file=sys.stderr, flush=True)
+    blog = lambda m: print("bench:", m, file=sys.stderr, flush=True)  # noqa: E731
+    blog(f"building workload {args.workload}")
     wl = make_workload(args.workload)
-    print(f"bench: {wl.name}, {wl.cells} cells, warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
+    blog(f"{wl.name}, {wl.cells} cells, warmup {args.warmup}, steps {args.steps}")
     stream = torch.cuda.current_stream()
-    ctx = lbfd.Context(wl.setup, wl.phi, stream=stream)
-    ctx.init_state(wl.T0, wl.Y0 if wl.setup["ns"] else None)
-    ctx.step(args.warmup)
-    ctx.synchronize()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    ctx.step(args.steps)
-    e1.record(stream)
-    ctx.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    ms_step = ms / args.steps
-    diag = ctx.diagnostics()
-    mlups = wl.cells * args.steps / (ms * 1e-3) / 1e6
-    # second pass: the same K steps with every step-kernel launch bracketed by
-    # HIP events on the kernel's stream, for the kernel's own mean duration
-    ctx.set_timing(True)
-    ctx.step(args.steps)
-    n_step, ms_kernel = ctx.kernel_time(lbfd.LBFD_KERNEL_STEP)
-    n_isl, ms_island = ctx.kernel_time(lbfd.LBFD_KERNEL_ISLAND)
-    ctx.set_timing(False)
-    bpc = ctx.bytes_per_cell()
-    bytes_launch = bpc * wl.cells
-    achieved = bytes_launch / (ms_kernel * 1e-3) / 1e9
-    traffic = traffic_from_profiles(args.workload, bytes_launch)
+    m = measure(wl, args.steps, args.warmup, args.settle_ms, stream=stream)
+    ctx, diag = m["ctx"], m["diag"]
+    bpc = survey_bytes_per_cell(wl.setup)
+    traffic = traffic_from_profiles(args.workload, ctx.bytes_per_cell() * wl.cells)
     prec = wl.setup.get("precision", "fp64")
     out = {
         "metric": METRIC,
-        "value": round(mlups, 2),
+        "value": round(m["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": round(m["ms_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -385,35 +481,36 @@ def main():
                    "lattice": "D2Q9" if wl.setup["dim"] == 2 else "D3Q19",
                    "species": wl.setup["ns"], "reactions": len(wl.setup["mech"]["A"]),
                    "precision": prec, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_cell": bpc,
-                     "bytes_per_launch": bytes_launch,
-                     "kernel": "step_kernel (fused LB+FD+chemistry+partials)",
-                     "kernel_ms": round(ms_kernel, 5), "kernel_launches": n_step,
-                     "island_ms": round(ms_island, 5), "island_launches": n_isl},
+        "settle_steps": m["settle"],
+        "roofline": roofline(wl, m, traffic),
         "diagnostics": {"mass": diag["mass"], "Tmax": diag["Tmax"], "umax": diag["umax"],
                         "n_flagged_fp64": diag["n_flagged_fp64"],
                         "n_nonfinite": diag["n_nonfinite"]},
-        "wall_s": round(wall, 3),
+        "wall_s": round(m["wall"], 3),
     }
     if wl.name.startswith("elongated_bed") and "_slab_" in wl.name:
-        print("bench: halo planes", file=sys.stderr, flush=True)
+        blog("halo planes")
         out["halo"] = halo_measure(ctx, stream)
-        out["halo"]["step_ms"] = round(ms_step, 4)
-    blog = lambda m: print("bench:", m, file=sys.stderr, flush=True)  # noqa: E731
+        out["halo"]["step_ms"] = round(m["ms_step"], 4)
+    del m, ctx
+    torch.cuda.empty_cache()
     if not args.no_surrogate and args.workload == "sphere_bed":
-        print("bench: surrogate vs exact chemistry (9-species bed)", file=sys.stderr, flush=True)
+        blog("surrogate vs exact chemistry (9-species bed)")
         out["surrogate"] = surrogate_measure(log=blog)
     elif not args.no_surrogate and args.workload == "elongated_bed":
         # the elongated bed's own surrogate: pairs from 2000 exact steps of it
-        del ctx
-        print("bench: surrogate vs exact chemistry (elongated bed)", file=sys.stderr, flush=True)
+        blog("surrogate vs exact chemistry (elongated bed)")
         out["surrogate"] = surrogate_measure(wl, steps=20, log=blog, sample_steps=2000,
                                              every=25, per_snapshot=25000, err_steps=200,
                                              sweep=False)
+    if not args.no_configs and args.workload == "sphere_bed":
+        # the other workloads of the method at their own sizes: the cylinder
+        # channel (D2Q9, FP64), the superquadric bed and the 67 M-cell
+        # elongated bed (9 species, FP32)
+        out["configs"] = [config_line(n, args.steps, args.warmup, args.settle_ms, blog)
+                          for n in ("cylinder", "superquadric_bed", "elongated_bed")]
     if not args.no_cpu_baseline:
-        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        blog("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     else:
         out["cpu_baseline"] = None

@@ -77,6 +77,7 @@ int      orc_step(orc_ctx* o, int32_t n, int32_t phase_mask);
 int      orc_read(const orc_ctx* o, int32_t field, int32_t comp, double* out);
 void     orc_diag(const orc_ctx* o, double* out /* ORC_D_LEN */);
 int32_t  orc_nthreads(void);
+void     orc_set_threads(int32_t n);  /* OpenMP threads of the next steps (n > 0) */
 
 /* unit hooks used by the pins */
 void orc_eq_source(int32_t dim, double rho, const double* u, double Ph, const double* G,

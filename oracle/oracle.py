@@ -74,6 +74,7 @@ def lib():
         L.orc_read.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp]
         L.orc_diag.argtypes = [C.c_void_p, dp]
         L.orc_nthreads.restype = C.c_int32
+        L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_eq_source.argtypes = [C.c_int32, C.c_double, dp, C.c_double, dp, dp, C.c_double,
                                     dp, dp]
         L.orc_lattice.argtypes = [C.c_int32, C.POINTER(C.c_int32), dp]
@@ -242,3 +243,8 @@ def reactor(setup, T, Y, nsteps):
 
 def nthreads():
     return int(lib().orc_nthreads())
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's next steps."""
+    lib().orc_set_threads(int(n))

@@ -156,34 +156,64 @@ def particle_distance(p: Particle, x, y, z, shape, periodic) -> np.ndarray:
     return p.r * (F ** (1.0 / n) - 1.0)
 
 
-def bed_phi(shape, particles, eta: float, periodic) -> np.ndarray:
-    """Union (max) of the particles' tanh phase fields on a [nz, ny, nx] grid."""
+def _particle_box(p: Particle, shape, eta: float, periodic):
+    """Cell index lists (x, y, z) of the box a particle's phase field reaches."""
     nz, ny, nx = shape
-    phi = np.zeros(shape, np.float64)
     reach = 2.0 * eta + 1.0
+    ext = (p.r * (float(np.max(p.axes)) / p.r if p.axes is not None else 1.0)) + reach
+    ext = max(ext, p.r * 1.6 + reach) if p.kind == "superquadric" else ext
+    idx = []
+    for a, n in enumerate((nx, ny, nz)):
+        lo = int(math.floor(p.centre[a] - ext))
+        hi = int(math.ceil(p.centre[a] + ext)) + 1
+        rng_ = np.arange(lo, hi)
+        if periodic[a]:
+            rng_ = np.mod(rng_, n)
+            rng_ = np.unique(rng_)
+        else:
+            rng_ = rng_[(rng_ >= 0) & (rng_ < n)]
+        idx.append(rng_)
+    return idx
+
+
+def _bed_phi_planes(shape, particles, eta, periodic, z0, z1):
+    """Planes z0 <= z < z1 of bed_phi (max over the particles reaching them)."""
+    nz, ny, nx = shape
+    phi = np.zeros((z1 - z0, ny, nx), np.float64)
     for p in particles:
-        ext = (p.r * (float(np.max(p.axes)) / p.r if p.axes is not None else 1.0)) + reach
-        ext = max(ext, p.r * 1.6 + reach) if p.kind == "superquadric" else ext
-        idx = []
-        for a, n in enumerate((nx, ny, nz)):
-            lo = int(math.floor(p.centre[a] - ext))
-            hi = int(math.ceil(p.centre[a] + ext)) + 1
-            rng_ = np.arange(lo, hi)
-            if periodic[a]:
-                rng_ = np.mod(rng_, n)
-                rng_ = np.unique(rng_)
-            else:
-                rng_ = rng_[(rng_ >= 0) & (rng_ < n)]
-            idx.append(rng_)
-        if any(len(i) == 0 for i in idx):
+        ix, iy, iz = _particle_box(p, shape, eta, periodic)
+        iz = iz[(iz >= z0) & (iz < z1)]
+        if len(ix) == 0 or len(iy) == 0 or len(iz) == 0:
             continue
-        zz, yy, xx = np.meshgrid(idx[2], idx[1], idx[0], indexing="ij")
+        zz, yy, xx = np.meshgrid(iz, iy, ix, indexing="ij")
         d = particle_distance(p, xx.astype(float), yy.astype(float), zz.astype(float), shape,
                               periodic)
         ph = phase_tanh(d, eta)
-        sub = phi[np.ix_(idx[2], idx[1], idx[0])]
-        phi[np.ix_(idx[2], idx[1], idx[0])] = np.maximum(sub, ph)
+        sel = np.ix_(iz - z0, iy, ix)
+        phi[sel] = np.maximum(phi[sel], ph)
     return phi
+
+
+def bed_phi(shape, particles, eta: float, periodic, workers=None) -> np.ndarray:
+    """Union (max) of the particles' tanh phase fields on a [nz, ny, nx] grid.
+
+    Large grids are computed in z-slabs by a pool of processes; each cell's
+    value is the same maximum of the same per-particle values either way."""
+    import os
+
+    nz, ny, nx = shape
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if nz * ny * nx >= (1 << 23) else 1
+    if workers <= 1 or nz < 2 * workers:
+        return _bed_phi_planes(shape, particles, eta, periodic, 0, nz)
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    bounds = np.linspace(0, nz, workers + 1).astype(int)
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        parts = list(ex.map(_bed_phi_planes, [shape] * workers, [particles] * workers,
+                            [eta] * workers, [periodic] * workers, bounds[:-1], bounds[1:]))
+    return np.concatenate(parts, axis=0)
 
 
 def sharp_solid(shape, particles, periodic) -> np.ndarray:
