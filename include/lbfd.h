@@ -119,7 +119,15 @@ typedef struct {
                                         a checkpoint restore also sets the P0 state
                                         (lbfd_set_p0_state).  0: P0 fixed             */
     double r_gas;                    /* closed domain: R / M_ref in the units of cp,
-                                        0 <= r_gas < cp                              */
+                                        0 <= r_gas < cp (the lagged dP0/dt term then
+                                        settles with the ratio r_gas/cp < 1)         */
+    double T_max;                    /* highest temperature the run is expected to
+                                        reach [K] (e.g. the flame temperature); the
+                                        stability rule (lbfd_stability) is evaluated
+                                        up to the largest of T_max, T_in, T_solid, the
+                                        Dirichlet face temperatures and, from
+                                        lbfd_init_state on, the initial state's
+                                        maximum.  0: no bound beyond those           */
 } lbfd_params;
 
 typedef struct {
@@ -166,34 +174,113 @@ typedef enum {
 /* phase bits of lbfd_step_phase (test hook; lbfd_step runs all three) */
 enum { LBFD_PHASE_LB = 1, LBFD_PHASE_FD = 2, LBFD_PHASE_CHEM = 4, LBFD_PHASE_ALL = 7 };
 
-/* Bytes of device workspace a grid needs (256-byte aligned base expected). */
+/* ------------------------------------------------------------------------
+ * Explicit-stability rule (host only, no device needed).  The FD transport is
+ * one forward-Euler step with first-order upwind convection, conservative
+ * central diffusion and the interface heat exchange (Sec. 3.3); the reaction
+ * step is n_sub explicit sub-steps of Eqs. 8 and 9.  Per cell the FD update is
+ * a convex combination of the old values (hence bounded, non-oscillating)
+ * when its diagonal weight 1 - (sum_faces lambda_f/(rho cp) + H/(rho cp) +
+ * sum_a |u_a|) stays positive.  Over the temperature range [T_lo, T_hi]:
+ *   tau_lo   = mu/(rho cs^2) + 1/2 at T_lo (viscosity and density grow and
+ *              fall with T), must exceed 0.501;
+ *   alpha_hi = lambda/(rho cp), D_hi = max_k lambda/(rho cp Le_k) at T_hi,
+ *              with the closure of the params (single gas, or the Wilke
+ *              mixture at the inlet composition) and rho of the inlet mixture;
+ *   h_hi     = A_T alpha_hi max(phi_f phi_s^2)/eta^2, the maximum 4/27 at
+ *              phi_s = 2/3;
+ *   u_sum    = sqrt(dim) 0.1, the low-Mach limit |u| <= 0.1;
+ *   fd_sum   = 2 dim max(alpha_hi, D_hi) + h_hi + u_sum, must be <= 0.9;
+ *   kappa_hi = max_k of species k's pseudo-first-order consumption rate,
+ *              sum_j nu_kj k_j prod_m [X_m]^(nu_mj - delta_mk) over the
+ *              forward and (reversible) reverse sides, at T_hi with
+ *              [X_m] = rho max(Y_in,m, 0.01)/M_m (every species counted at
+ *              one per cent at least, so that products absent at the inlet
+ *              still count);
+ *   h_kappa  = kappa_hi / n_sub, must be <= 0.5.
+ * lbfd_set_params, lbfd_set_mechanism and lbfd_init_state apply this rule and
+ * return LBFD_E_INVAL (message naming the failed bound) when it fails.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double T_lo, T_hi;   /* temperature range the bounds were evaluated over [K]  */
+    double tau_lo;       /* relaxation time at T_lo                               */
+    double alpha_hi, D_hi, h_hi, u_sum;
+    double fd_sum;       /* must be <= 0.9                                        */
+    double kappa_hi;     /* 0 without a mechanism                                 */
+    double h_kappa;      /* must be <= 0.5                                        */
+    int32_t violated;    /* bits: 1 tau_lo, 2 fd_sum, 4 h_kappa, 8 a non-finite
+                            rate or property                                      */
+} lbfd_stability_report;
+
+/* Evaluate the rule for a grid, params and mechanism (mech may be NULL: no
+ * reaction bound, and a Wilke closure then needs it and is skipped) over the
+ * temperatures T_in, T_solid, the Dirichlet faces, params->T_max and the
+ * extra range [T_lo, T_hi] (pass 0, 0 for none).  Fills *out (may be NULL);
+ * LBFD_OK when every bound holds, LBFD_E_INVAL otherwise or for bad
+ * arguments. */
+lbfd_status lbfd_stability(const lbfd_grid* grid, const lbfd_params* params,
+                           const lbfd_mechanism* mech, double T_lo, double T_hi,
+                           lbfd_stability_report* out);
+
+/* Bytes of device workspace a grid needs (256-byte aligned base expected).
+ * The grid is the paper's Cartesian domain of volume elements (Sec. 2, the
+ * averaging cells of Eq. def-volume-average; lattice units, one cell per
+ * element).  LBFD_E_INVAL for a grid the library cannot hold (see
+ * lbfd_grid; at most 2^31 / Q cells, 32-bit plane offsets). */
 lbfd_status lbfd_workspace_bytes(const lbfd_grid* grid, size_t* bytes);
 
-/* Create a context on the current HIP device.  dev_workspace: caller-owned
- * device buffer of at least lbfd_workspace_bytes; hip_stream: hipStream_t (or
- * NULL for the null stream) on which every kernel of this context runs. */
+/* Create a context for one grid (Sec. 2, Eq. def-volume-average: the cells
+ * over which every field is averaged) on the current HIP device.
+ * dev_workspace: caller-owned device buffer of at least lbfd_workspace_bytes,
+ * 256-byte aligned (LBFD_E_INVAL otherwise, LBFD_E_NOMEM when too small);
+ * hip_stream: hipStream_t (or NULL for the null stream) on which every kernel
+ * of this context runs.  *out receives the context (host memory owned by the
+ * library until lbfd_destroy); LBFD_E_DEVICE when no device is current. */
 lbfd_status lbfd_create(const lbfd_grid* grid, void* dev_workspace, size_t bytes,
                         void* hip_stream, lbfd_ctx** out);
 
-/* Static solid phase field phi_s in [0, 1] (host, nx*ny*nz doubles). */
+/* Static solid phase field phi_s in [0, 1] (host, nx*ny*nz doubles, x
+ * fastest): the volume fraction of the solid phase in each cell (Sec. 2, Eq.
+ * phase-field-definition), e.g. from the diffuse profile of Eq. def-phi; the
+ * fluid fraction is 1 - phi_s.  LBFD_E_INVAL for values outside [0, 1]. */
 lbfd_status lbfd_set_phase_field(lbfd_ctx* ctx, const double* phi_solid);
 
-/* Reaction mechanism; n_species must equal the grid's. */
+/* Reaction mechanism of the sources omega_k = M_k sum_j s_kj Q_j (Sec. 3.2.2,
+ * Eq. 8) and the heat release omega_T = -sum_k dh_f,k omega_k (Sec. 3.3,
+ * Eq. 9), with mass-action rates of progress and Arrhenius rate constants;
+ * M_k also enters the EOS (Eq. rho-in-terms-of-P0-and-T) and the Wilke rules
+ * (Sec. 4.4, Eqs. muT_mix, phi_mix, conduct_mix).  Host tables, copied
+ * during the call.  n_species must equal the grid's.  LBFD_E_INVAL for bad
+ * tables, orders beyond the limits in lbfd_mechanism, or a mechanism that
+ * breaks the stability rule with the params already set. */
 lbfd_status lbfd_set_mechanism(lbfd_ctx* ctx, const lbfd_mechanism* mech);
 
-/* Physical and coupling parameters; rejects unstable values (tau at the inlet
- * state <= 0.5 + 1e-3, |u_in| > 0.1, eta <= 0, n_sub < 1, ...). */
+/* Physical and coupling parameters (host struct, copied): the interface drag
+ * coefficient A_u and thickness eta (Sec. 3.2.1, Eq. Fdrag-empirical-law), the
+ * heat-exchange coefficient A_T and solid temperature (Sec. 3.3, Eq.
+ * diffusion-heat-flux-3), Sutherland viscosity and conductivity (Sec. 4, Eqs.
+ * muT and lambdaT), the inlet state fixing the EOS reference (Sec. 3.1, Eq.
+ * rho-in-terms-of-P0-and-T) and the boundary values.  LBFD_E_INVAL for
+ * non-physical values (eta, cp, Pr, rho_in, T_in, nu_in, T_solid <= 0,
+ * |u_in| > 0.1, n_sub outside 1..4096, inlet fractions not summing to 1) and
+ * for parameters breaking the stability rule (lbfd_stability); the context
+ * is then unchanged.  May be called between steps. */
 lbfd_status lbfd_set_params(lbfd_ctx* ctx, const lbfd_params* params);
 
-/* Initial state (host FP64): T[N], Y[ns*N] (NULL iff ns == 0), u[dim*N] or
- * NULL (rest).  Sets rho from the EOS, divu = 0, P_h = 0 and the populations
- * to equilibrium; clears the diagnostics.  Needs phase field, params and (ns >
- * 0) mechanism first. */
+/* Initial state (host FP64, x fastest): T[N], Y[ns*N] (NULL iff ns == 0),
+ * u[dim*N] or NULL (rest).  Sets rho from the EOS (Sec. 3.1, Eq.
+ * rho-in-terms-of-P0-and-T), divu = 0, P_h = 0 and the populations to the
+ * equilibrium of Eqs. eq-pop-f and eq-pop-g; clears the diagnostics.  Needs
+ * phase field, params and (ns > 0) mechanism first (LBFD_E_STATE).
+ * LBFD_E_INVAL for non-positive or non-finite T, or for a state whose
+ * temperatures break the stability rule (the previous state then stays). */
 lbfd_status lbfd_init_state(lbfd_ctx* ctx, const double* T, const double* Y, const double* u);
 
-/* Overwrite the post-stream populations (Q*N doubles, natural layout) and the
- * thermal divergence (N doubles, may be NULL); together with lbfd_init_state
- * this restores a checkpoint written with lbfd_read. */
+/* Overwrite the post-stream populations g_i of Eq. pop-g (Q*N doubles,
+ * natural layout, direction-major) and the thermal divergence of the source
+ * term of Eq. body-force (N doubles, may be NULL); together with
+ * lbfd_init_state this restores a checkpoint written with lbfd_read.
+ * LBFD_E_INVAL for non-finite values; LBFD_E_STATE before lbfd_init_state. */
 lbfd_status lbfd_set_populations(lbfd_ctx* ctx, const double* g, const double* divu);
 
 /* Closed domain (Sec. 3.1): the thermodynamic-pressure state that a checkpoint
@@ -206,7 +293,9 @@ lbfd_status lbfd_set_populations(lbfd_ctx* ctx, const double* g, const double* d
 lbfd_status lbfd_get_p0_state(lbfd_ctx* ctx, double* out);
 lbfd_status lbfd_set_p0_state(lbfd_ctx* ctx, const double* in);
 
-/* Enqueue n coupled steps on the context's stream; returns without waiting. */
+/* Enqueue n coupled steps on the context's stream (LB, then FD transport,
+ * then reactions, as listed at the top of this file: Sec. 3.3 and Eqs. 8, 9);
+ * returns without waiting.  LBFD_E_STATE before lbfd_init_state. */
 lbfd_status lbfd_step(lbfd_ctx* ctx, int32_t n);
 
 /* Enqueue n steps running only the phases in phase_mask (test hook).  Without
@@ -214,17 +303,26 @@ lbfd_status lbfd_step(lbfd_ctx* ctx, int32_t n);
  * enter the reaction step unchanged; without CHEM no reaction is applied. */
 lbfd_status lbfd_step_phase(lbfd_ctx* ctx, int32_t n, int32_t phase_mask);
 
-/* Copy one field component to host (waits for the stream). */
+/* Copy one field component to host (x fastest, N doubles; waits for the
+ * stream): the low-Mach state of Sec. 3.1 -- rho (EOS of the current T, Y_k),
+ * u and the hydrodynamic pressure P_h (moments of the current populations,
+ * Eqs. eq-pop-f, eq-pop-g), T, Y_k -- the populations, or the thermal
+ * divergence.  LBFD_E_INVAL for an unknown field or component. */
 lbfd_status lbfd_read(lbfd_ctx* ctx, int32_t field, int32_t component, double* host_out);
 
-/* Conservation sums of the state after the last step and cumulative counters
- * (waits for the stream); returns LBFD_E_NUMERIC if n_nonfinite > 0. */
+/* Conservation sums of the state after the last step, FP64 (the integrals
+ * of mass, species mass and enthalpy of the conservation laws of Sec. 3.1,
+ * Eqs. mass-cons, species-cons, energy-cons, over the cells), and cumulative
+ * counters (waits for the stream); returns LBFD_E_NUMERIC if n_nonfinite >
+ * 0, with *out filled. */
 lbfd_status lbfd_diagnostics(lbfd_ctx* ctx, lbfd_diag* out);
 
 /* Wait for the context's stream. */
 lbfd_status lbfd_synchronize(lbfd_ctx* ctx);
 
-/* Algorithmic HBM bytes one cell moves in one lbfd_step on this grid. */
+/* Algorithmic HBM bytes one cell moves in one lbfd_step on this grid: each
+ * array the fused step kernel reads or writes, once (populations in place,
+ * T and Y_k read and written, divergence read and written, phi read). */
 lbfd_status lbfd_step_bytes_per_cell(const lbfd_ctx* ctx, double* bytes);
 
 /* ------------------------------------------------------------------------
@@ -317,25 +415,37 @@ lbfd_status lbfd_trainer_gradient(lbfd_trainer* tr, const float* x, const float*
  * (any may be NULL; waits). */
 lbfd_status lbfd_trainer_export(lbfd_trainer* tr, float* weights, float* norm, float* envelope);
 lbfd_status lbfd_trainer_destroy(lbfd_trainer* tr);
+
 const char* lbfd_trainer_last_error(const lbfd_trainer* tr);
 
 /* ------------------------------------------------------------------------
  * Halo planes: the strided copies that a decomposition of the grid into slabs
- * along x exchanges between neighbouring GPUs each step (the one-cell
- * stencils of the LB streaming, Sec. 2.2, and of the FD transport, Eqs. 5
- * and 6, reach one plane across a slab face).  For the plane x (0 <= x < nx)
- * and the direction dir (-1 or +1), the buffer holds, plane after plane and
- * [z][y] within a plane, the population slots as stored of the directions
- * with c_x = dir (5 in D3Q19, 3 in D2Q9), then T and Y_1..Y_ns of the
- * current state, in the device precision: lbfd_halo_bytes bytes.  Pack
- * copies the plane into the buffer, unpack copies a buffer into the plane.
- * A rightward exchange packs (nx - 2, +1) on one slab and unpacks it at
- * (0, +1) on its right neighbour.  dev_buf: caller-owned device memory;
- * enqueued on the context's stream; LBFD_E_INVAL for x or dir out of range.
+ * along x exchanges between neighbouring slabs after every step (the one-cell
+ * stencils of the LB streaming, Eq. pop-g, and of the FD transport, Eqs.
+ * volume-averaged-species-equation-5 and energy-transport-DI-version, reach
+ * one plane across a slab face).  A slab context holds its own planes
+ * x = 1 .. nx - 2 and one halo plane on each side (x = 0 copies the left
+ * neighbour's last own plane, x = nx - 1 the right neighbour's first); its x
+ * faces are periodic.  After every lbfd_step(ctx, 1) each slab packs both
+ * faces (face -1: towards its left neighbour, +1: towards its right one) and
+ * then unpacks, on each face, the buffer its neighbour packed for it; the
+ * own planes then evolve bitwise as in the undivided grid.  What travels
+ * follows the AA parity of the state: T and Y_k of the own boundary plane
+ * (as stored: T - T_solid in FP32 mode, so neighbours need equal T_solid)
+ * and 5 population planes (3 in D2Q9; as stored: 36 g_i in FP32 mode) --
+ * after an even
+ * step the own boundary
+ * plane's slots with c_x = -face, which become the neighbour's halo slots;
+ * after an odd step the halo plane's slots with c_x = face, the populations
+ * the step pushed across the face, which become the neighbour's own slots.
+ * Buffer: plane after plane, [z][y] within a plane, populations then T then
+ * Y_1..Y_ns, in the device precision: lbfd_halo_bytes bytes.  dev_buf:
+ * caller-owned device memory; enqueued on the context's stream; LBFD_E_INVAL
+ * for a face other than -1 / +1 or nx < 3; LBFD_E_STATE before init_state.
  * ------------------------------------------------------------------------ */
 lbfd_status lbfd_halo_bytes(const lbfd_ctx* ctx, size_t* bytes);
-lbfd_status lbfd_halo_pack(lbfd_ctx* ctx, int32_t x, int32_t dir, void* dev_buf);
-lbfd_status lbfd_halo_unpack(lbfd_ctx* ctx, int32_t x, int32_t dir, const void* dev_buf);
+lbfd_status lbfd_halo_pack(lbfd_ctx* ctx, int32_t face, void* dev_buf);
+lbfd_status lbfd_halo_unpack(lbfd_ctx* ctx, int32_t face, const void* dev_buf);
 
 /* Per-kernel launch timing (measurement hook).  While enabled, every launch
  * of the fused step kernel, of the FP64 reaction-island kernel and of the

@@ -64,10 +64,15 @@ struct Par {
     R dp0_term;       // closed domain: P0_in (p^n - p^{n-1}), the dP0/dt of the step
     R dlnp0;          // closed domain: (p^n - p^{n-1}) / p^n
     R inv_T_in;       // 1 / T_in, rounded once on the host
+    R T_ref;          // the temperature planes hold T - T_ref: T_solid in FP32 mode
+                      // (cells inside the particles sit at T_solid, where the
+                      // stored offset is then exact to far below a kelvin's ulp),
+                      // 0 in FP64 mode (the planes hold T itself)
+    R Ts_rel;         // T_solid - T_ref
     R theta_ign, h_sub;
     R u_in[3], F_b[3];
     R inlet_eq[19];   // rho_in c_s^2 e_j(u_in): the inlet equilibria less their P_h part
-    R fd_face[6][1 + MAXS];
+    R fd_face[6][1 + MAXS];  // Dirichlet face values: T - T_ref, then Y_k
     R rD_fac[MAXS];   // 1/(cp Le_k)
     R M[MAXS], invM[MAXS], dhf[MAXS], mu_star[MAXS];
     R inv_mu_star[MAXS];  // 1 / mu_star (mu_star = 1 for padding species)
@@ -78,8 +83,17 @@ struct Par {
 
 // ------------------------------------------------------------------ lattice
 template <int D> struct Lat;
+// In FP32 mode the populations are stored scaled by 36 (G_i = 36 g_i): the
+// lattice weights then become the small integers k_i = 36 w_i, exact in FP32,
+// so that the collision's sums over the directions reproduce the weights'
+// moments exactly (sum w = 1, sum w c c = cs^2 I).  With the weights rounded
+// to FP32 (their sum is 1 + 1.5e-8 in D3Q19) every FP32 collision added a
+// small pressure and momentum bias of the same sign, and after 1000 steps the
+// velocity had drifted by up to 2e-5 of its maximum.  FP64 mode stores g
+// itself with the weights in FP64.
 template <> struct Lat<2> {
     static constexpr int Q = 9;
+    static constexpr int k[9] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
     static constexpr int cx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
     static constexpr int cy[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
     static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -88,6 +102,7 @@ template <> struct Lat<2> {
 };
 template <> struct Lat<3> {
     static constexpr int Q = 19;
+    static constexpr int k[19] = {12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
     static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
     static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
     static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -97,6 +112,20 @@ template <> struct Lat<3> {
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 };
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// Stored populations = scale * g: 36 in FP32 mode, 1 in FP64 mode.
+template <typename R>
+struct Pop {
+    static constexpr double scale = sizeof(R) == 4 ? 36.0 : 1.0;
+    static constexpr double inv = sizeof(R) == 4 ? 1.0 / 36.0 : 1.0;  // S0 = inv sum
+    static constexpr double mom = sizeof(R) == 4 ? 3.0 / 36.0 : 3.0;  // m = mom sum c
+};
+// The weight of direction i on the stored scale: the integer 36 w_i in FP32
+// mode, w_i in FP64 mode.
+template <typename R, int D>
+__host__ __device__ constexpr double pop_w(int i) {
+    return sizeof(R) == 4 ? (double)Lat<D>::k[i] : Lat<D>::w[i];
+}
 
 // ------------------------------------------------------------- arithmetic
 // FP32 mode uses the hardware reciprocal / square root / exp2 / log2
@@ -374,13 +403,15 @@ struct StepArgs {
 };
 
 // Halo planes of one x face (the strided copies a slab decomposition along x
-// exchanges): plane p of the list, cells (x_face, y, z) <-> buf[p][z][y].
+// exchanges): entry p of the list is field plane `plane[p]` at x = xs[p],
+// cells (xs[p], y, z) <-> buf[p][z][y].
 constexpr int HALO_MAX_PLANES = 24;
 static_assert(HALO_MAX_PLANES >= 5 + 1 + MAXS, "halo plane table");
 template <typename R>
 struct HaloArgs {
     R* plane[HALO_MAX_PLANES];
-    int nplanes, nx, ny, nz, x;
+    int xs[HALO_MAX_PLANES];
+    int nplanes, nx, ny, nz;
     R* buf;
     int pack;  // 1: planes -> buf, 0: buf -> planes
 };

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -195,6 +196,8 @@ struct lbfd_ctx {
     HostMech mech;
     bool have_phi = false, have_params = false, have_mech = false, have_state = false;
     int cur = 0, odd = 0;
+    double state_T[2] = {0.0, 0.0};  // min and max T of the initial state
+    double T_ref = 0.0;  // the temperature planes hold T - T_ref (FP32: T_solid at init_state)
     int64_t steps = 0;
     std::string err;
     // launch timing: event pairs per kernel kind, reused across enable cycles
@@ -229,6 +232,161 @@ double wilke(double muk, double muj, double Mk, double Mj) {
     return a * a / (std::sqrt(8.0) * std::sqrt(1.0 + Mk / Mj));
 }
 
+// Validated host copy of a mechanism table.
+lbfd_status mech_from_abi(const lbfd_mechanism* m, HostMech& h, std::string& msg) {
+    if (m->n_reactions < 0 || m->n_reactions > LBFD_MAX_REACTIONS)
+        return msg = "n_reactions out of range", LBFD_E_INVAL;
+    const int ns = m->n_species, nr = m->n_reactions;
+    if (ns < 0 || ns > LBFD_MAX_SPECIES) return msg = "n_species out of range", LBFD_E_INVAL;
+    if (ns > 0 && (!m->M || !m->dhf || !m->mu_star)) return msg = "null table", LBFD_E_INVAL;
+    if (nr > 0 && (!m->nu_f || !m->nu_r || !m->A || !m->beta || !m->theta || !m->reversible ||
+                   !m->lnKc_a || !m->lnKc_b))
+        return msg = "null table", LBFD_E_INVAL;
+    h = HostMech();
+    h.ns = ns;
+    h.nr = nr;
+    for (int k = 0; k < ns; ++k) {
+        if (!(m->M[k] > 0.0) || !(m->mu_star[k] > 0.0) || !std::isfinite(m->dhf[k]) ||
+            !std::isfinite(m->M[k]) || !std::isfinite(m->mu_star[k]))
+            return msg = "bad species data", LBFD_E_INVAL;
+        h.M.push_back(m->M[k]);
+        h.dhf.push_back(m->dhf[k]);
+        h.mu_star.push_back(m->mu_star[k]);
+    }
+    for (int j = 0; j < nr; ++j) {
+        if (!(m->A[j] >= 0.0) || !std::isfinite(m->A[j]) || !std::isfinite(m->beta[j]) ||
+            !std::isfinite(m->theta[j]) || !std::isfinite(m->lnKc_a[j]) ||
+            !std::isfinite(m->lnKc_b[j]))
+            return msg = "bad rate data", LBFD_E_INVAL;
+        h.A.push_back(m->A[j]);
+        h.beta.push_back(m->beta[j]);
+        h.theta.push_back(m->theta[j]);
+        h.lnKc_a.push_back(m->lnKc_a[j]);
+        h.lnKc_b.push_back(m->lnKc_b[j]);
+        h.rev.push_back(m->reversible[j] ? 1 : 0);
+        int order_f = 0, order_r = 0;
+        for (int k = 0; k < ns; ++k) {
+            const int f = m->nu_f[j * ns + k], r = m->nu_r[j * ns + k];
+            if (f < 0 || f > 3 || r < 0 || r > 3)
+                return msg = "stoichiometric coefficients must be 0..3", LBFD_E_INVAL;
+            h.nu_f.push_back(f);
+            h.nu_r.push_back(r);
+            order_f += f;
+            order_r += r;
+        }
+        if (order_f > 4 || order_r > 4) return msg = "reaction order of a side above 4", LBFD_E_INVAL;
+    }
+    return LBFD_OK;
+}
+
+// ------------------------------------------------------ stability rule
+// Host closures of the check (the same definitions as the kernels' closures,
+// in FP64): Sutherland ratio, and viscosity / conductivity of one state.
+double host_sutherland(const lbfd_params& p, double T) {
+    if (p.mu_model == 0) return 1.0;
+    const double x = T / p.T_in;
+    return x * std::sqrt(x) * (p.T_in + p.sutherland_S) / (T + p.sutherland_S);
+}
+void host_transport(const lbfd_params& p, int ns, const HostMech* m, double T, const double* Y,
+                    double& mu, double& lam) {
+    const double mu0 = p.rho_in * p.nu_in * host_sutherland(p, T);
+    if (p.transport_model == 1 && ns > 0 && m) {
+        double im = 0.0, X[LBFD_MAX_SPECIES];
+        for (int k = 0; k < ns; ++k) im += Y[k] / m->M[k];
+        for (int k = 0; k < ns; ++k) X[k] = Y[k] / (m->M[k] * im);
+        double mm = 0.0, l1 = 0.0, l2 = 0.0;
+        for (int k = 0; k < ns; ++k) {
+            double den = 0.0;
+            for (int j = 0; j < ns; ++j)
+                den += wilke(m->mu_star[k], m->mu_star[j], m->M[k], m->M[j]) * X[j];
+            const double muk = m->mu_star[k] * mu0, lk = muk * p.cp / p.Pr;
+            if (X[k] > 0.0) mm += muk * X[k] / den;
+            l1 += X[k] * lk;
+            l2 += X[k] / lk;
+        }
+        mu = mm;
+        lam = 0.5 * (l1 + 1.0 / l2);
+        return;
+    }
+    mu = mu0;
+    lam = mu0 * p.cp / p.Pr;
+}
+
+// The rule of lbfd_stability over [min(T_lo, given temperatures), max(T_hi, ...)].
+lbfd_status stability_eval(const lbfd_grid& g, const lbfd_params& p, const HostMech* m,
+                           double T_lo, double T_hi, lbfd_stability_report& r, std::string& msg) {
+    std::memset(&r, 0, sizeof(r));
+    const int ns = g.n_species, d = g.dim;
+    double lo = p.T_in, hi = p.T_in;
+    auto take = [&](double t) {
+        if (t > 0.0 && std::isfinite(t)) {
+            lo = std::min(lo, t);
+            hi = std::max(hi, t);
+        }
+    };
+    take(p.T_solid);
+    take(p.T_max);
+    for (int f = 0; f < 6; ++f)
+        if (g.fd_bc[f] == LBFD_FD_DIRICHLET) take(p.fd_face[f][0]);
+    take(T_lo);
+    take(T_hi);
+    r.T_lo = lo;
+    r.T_hi = hi;
+    // density of the inlet mixture (its molar mass is the EOS reference, so
+    // rho = rho_in T_in / T); viscosity and conductivity of the closure
+    double Y[LBFD_MAX_SPECIES];
+    for (int k = 0; k < ns; ++k) Y[k] = p.Y_in[k];
+    double mu, lam;
+    host_transport(p, ns, m, lo, Y, mu, lam);
+    const double rho_lo = p.rho_in * p.T_in / lo;
+    r.tau_lo = mu / (rho_lo / 3.0) + 0.5;
+    host_transport(p, ns, m, hi, Y, mu, lam);
+    const double rho_hi = p.rho_in * p.T_in / hi;
+    r.alpha_hi = lam / (rho_hi * p.cp);
+    double le_min = 1.0;
+    for (int k = 0; k < ns; ++k) le_min = std::min(le_min, p.Le[k]);
+    r.D_hi = ns > 0 ? r.alpha_hi / le_min : 0.0;
+    r.h_hi = p.A_T * r.alpha_hi * (4.0 / 27.0) / (p.eta * p.eta);
+    r.u_sum = std::sqrt((double)d) * 0.1;
+    r.fd_sum = 2.0 * d * std::max(r.alpha_hi, r.D_hi) + r.h_hi + r.u_sum;
+    // pseudo-first-order consumption rate of each species at T_hi
+    if (m && ns > 0 && m->nr > 0) {
+        double X[LBFD_MAX_SPECIES], kap[LBFD_MAX_SPECIES] = {0.0};
+        for (int k = 0; k < ns; ++k) X[k] = rho_hi * std::max(p.Y_in[k], 0.01) / m->M[k];
+        for (int j = 0; j < m->nr; ++j) {
+            const double lkf =
+                std::log(std::max(m->A[j], 1e-300)) + m->beta[j] * std::log(hi) - m->theta[j] / hi;
+            for (int side = 0; side < (m->rev[j] ? 2 : 1); ++side) {
+                const int* nu = side == 0 ? &m->nu_f[j * ns] : &m->nu_r[j * ns];
+                const double lk = side == 0 ? lkf : lkf - (m->lnKc_a[j] + m->lnKc_b[j] / hi);
+                if (m->A[j] == 0.0) continue;
+                for (int k = 0; k < ns; ++k) {
+                    if (nu[k] == 0) continue;
+                    double v = nu[k] * std::exp(lk);
+                    for (int q = 0; q < ns; ++q) v *= std::pow(X[q], nu[q] - (q == k ? 1 : 0));
+                    kap[k] += v;
+                }
+            }
+        }
+        for (int k = 0; k < ns; ++k) r.kappa_hi = std::max(r.kappa_hi, kap[k]);
+        r.h_kappa = r.kappa_hi / p.n_sub;
+    }
+    if (!std::isfinite(r.tau_lo) || !std::isfinite(r.fd_sum) || !std::isfinite(r.h_kappa))
+        r.violated |= 8;
+    if (!(r.tau_lo > 0.5 + 1e-3)) r.violated |= 1;
+    if (!(r.fd_sum <= 0.9)) r.violated |= 2;
+    if (!(r.h_kappa <= 0.5)) r.violated |= 4;
+    if (!r.violated) return LBFD_OK;
+    char buf[512];
+    std::snprintf(buf, sizeof(buf),
+                  "explicit stability over %.1f..%.1f K: tau(T_lo) = %.4g (> 0.501), "
+                  "2 dim max(alpha, D) + H/(rho cp) + sum|u| = %.4g (<= 0.9; alpha %.4g, D %.4g, "
+                  "H/(rho cp) %.4g, sum|u| %.4g), kappa/n_sub = %.4g (<= 0.5)",
+                  lo, hi, r.tau_lo, r.fd_sum, r.alpha_hi, r.D_hi, r.h_hi, r.u_sum, r.h_kappa);
+    msg = buf;
+    return LBFD_E_INVAL;
+}
+
 template <typename R>
 Par<R> build_par(const lbfd_ctx* c) {
     Par<R> P;
@@ -243,10 +401,16 @@ Par<R> build_par(const lbfd_ctx* c) {
     P.n_sub = p.n_sub;
     P.mu_model = p.mu_model;
     P.transport = p.transport_model;
+    // temperature planes hold T - T_ref (FP32 mode: T_solid of the params the
+    // state was initialised with; FP64 mode: 0)
+    const double T_ref = c->T_ref;
+    P.T_ref = (R)T_ref;
+    P.Ts_rel = (R)(p.T_solid - T_ref);
     for (int f = 0; f < 6; ++f) {
         P.lb_bc[f] = g.lb_bc[f];
         P.fd_bc[f] = g.fd_bc[f];
-        for (int k = 0; k <= c->ns; ++k) P.fd_face[f][k] = (R)p.fd_face[f][k];
+        P.fd_face[f][0] = (R)(p.fd_face[f][0] - T_ref);
+        for (int k = 1; k <= c->ns; ++k) P.fd_face[f][k] = (R)p.fd_face[f][k];
     }
     P.A_u = (R)p.A_u;
     P.A_T = (R)p.A_T;
@@ -363,6 +527,16 @@ Par<R> build_par(const lbfd_ctx* c) {
 
 bool ready_for_tables(const lbfd_ctx* c) { return c->have_params && (c->ns == 0 || c->have_mech); }
 
+// The stability rule for a context with the given params and mechanism, over
+// the temperatures of the initial state when one was set.
+lbfd_status check_stable(lbfd_ctx* c, const lbfd_params& p, const HostMech* m) {
+    lbfd_stability_report r;
+    std::string msg;
+    const lbfd_status st = stability_eval(c->grid, p, m, c->have_state ? c->state_T[0] : 0.0,
+                                          c->have_state ? c->state_T[1] : 0.0, r, msg);
+    return st ? fail(c, st, msg) : LBFD_OK;
+}
+
 // Closed domain: the sum of M / T over the current state and the P0 update
 // (mode as in p0_update_kernel), on the context's stream.
 lbfd_status launch_p0(lbfd_ctx* c, int mode) {
@@ -403,11 +577,18 @@ lbfd_status upload_tables(lbfd_ctx* c) {
     return hip_check(c, hipStreamSynchronize(c->stream), "upload parameters");
 }
 
-// host FP64 -> device field of the context's precision
-lbfd_status upload_field(lbfd_ctx* c, size_t off, const double* src, size_t n) {
+// host FP64 -> device field of the context's precision (minus `shift`,
+// applied in FP64 before the rounding: the temperature planes)
+lbfd_status upload_field(lbfd_ctx* c, size_t off, const double* src, size_t n,
+                         double shift = 0.0, double scale = 1.0) {
+    if (scale != 1.0) {  // stored as scale * value (the populations)
+        std::vector<double> tmp(n);
+        for (size_t i = 0; i < n; ++i) tmp[i] = src[i] * scale;
+        return upload_field(c, off, tmp.data(), n, shift, 1.0);
+    }
     if (c->fp32) {
         std::vector<float> tmp(n);
-        for (size_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
+        for (size_t i = 0; i < n; ++i) tmp[i] = (float)(src[i] - shift);
         lbfd_status st = hip_check(
             c, hipMemcpyAsync(dptr<char>(c, off), tmp.data(), n * 4, hipMemcpyHostToDevice, c->stream),
             "upload");
@@ -420,7 +601,14 @@ lbfd_status upload_field(lbfd_ctx* c, size_t off, const double* src, size_t n) {
     return hip_check(c, hipStreamSynchronize(c->stream), "upload");
 }
 
-lbfd_status download_field(lbfd_ctx* c, size_t off, double* dst, size_t n) {
+lbfd_status download_field(lbfd_ctx* c, size_t off, double* dst, size_t n, double shift = 0.0,
+                           double scale = 1.0) {
+    if (scale != 1.0) {
+        lbfd_status st = download_field(c, off, dst, n, shift, 1.0);
+        if (st) return st;
+        for (size_t i = 0; i < n; ++i) dst[i] /= scale;
+        return LBFD_OK;
+    }
     if (c->fp32) {
         std::vector<float> tmp(n);
         lbfd_status st = hip_check(
@@ -429,7 +617,7 @@ lbfd_status download_field(lbfd_ctx* c, size_t off, double* dst, size_t n) {
         if (st) return st;
         st = hip_check(c, hipStreamSynchronize(c->stream), "download");
         if (st) return st;
-        for (size_t i = 0; i < n; ++i) dst[i] = tmp[i];
+        for (size_t i = 0; i < n; ++i) dst[i] = (double)tmp[i] + shift;
         return LBFD_OK;
     }
     lbfd_status st = hip_check(
@@ -439,6 +627,8 @@ lbfd_status download_field(lbfd_ctx* c, size_t off, double* dst, size_t n) {
 }
 
 size_t elem(const lbfd_ctx* c) { return c->fp32 ? 4 : 8; }
+// stored populations = scale * g (FP32: 36, so that the weights are integers)
+double pop_scale(const lbfd_ctx* c) { return c->fp32 ? Pop<float>::scale : Pop<double>::scale; }
 
 lbfd_status validate_grid(const lbfd_grid* g, std::string& msg) {
     if (!g) return msg = "null grid", LBFD_E_INVAL;
@@ -602,6 +792,30 @@ lbfd_status set_device(lbfd_ctx* c) { return hip_check(c, hipSetDevice(c->device
 
 extern "C" {
 
+lbfd_status lbfd_stability(const lbfd_grid* grid, const lbfd_params* params,
+                           const lbfd_mechanism* mech, double T_lo, double T_hi,
+                           lbfd_stability_report* out) {
+    std::string msg;
+    if (!params) return LBFD_E_INVAL;
+    lbfd_status st = validate_grid(grid, msg);
+    if (st) return st;
+    HostMech h;
+    if (mech) {
+        if (mech->n_species != grid->n_species) return LBFD_E_INVAL;
+        if ((st = mech_from_abi(mech, h, msg))) return st;
+    }
+    auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+    if (!pos(params->eta) || !pos(params->cp) || !pos(params->Pr) || !pos(params->rho_in) ||
+        !pos(params->T_in) || !(params->nu_in >= 0.0) || params->n_sub < 1)
+        return LBFD_E_INVAL;
+    for (int k = 0; k < grid->n_species; ++k)
+        if (!pos(params->Le[k])) return LBFD_E_INVAL;
+    lbfd_stability_report r;
+    st = stability_eval(*grid, *params, mech ? &h : nullptr, T_lo, T_hi, r, msg);
+    if (out) *out = r;
+    return st;
+}
+
 lbfd_status lbfd_workspace_bytes(const lbfd_grid* grid, size_t* bytes) {
     std::string msg;
     lbfd_status st = validate_grid(grid, msg);
@@ -661,48 +875,12 @@ lbfd_status lbfd_set_phase_field(lbfd_ctx* c, const double* phi) {
 lbfd_status lbfd_set_mechanism(lbfd_ctx* c, const lbfd_mechanism* m) {
     if (!c || !m) return LBFD_E_INVAL;
     if (m->n_species != c->ns) return fail(c, LBFD_E_INVAL, "mechanism species != grid species");
-    if (m->n_reactions < 0 || m->n_reactions > LBFD_MAX_REACTIONS)
-        return fail(c, LBFD_E_INVAL, "n_reactions out of range");
-    const int ns = c->ns, nr = m->n_reactions;
-    if (ns > 0 && (!m->M || !m->dhf || !m->mu_star)) return fail(c, LBFD_E_INVAL, "null table");
-    if (nr > 0 && (!m->nu_f || !m->nu_r || !m->A || !m->beta || !m->theta || !m->reversible ||
-                   !m->lnKc_a || !m->lnKc_b))
-        return fail(c, LBFD_E_INVAL, "null table");
     HostMech h;
-    h.ns = ns;
-    h.nr = nr;
-    for (int k = 0; k < ns; ++k) {
-        if (!(m->M[k] > 0.0) || !(m->mu_star[k] > 0.0) || !std::isfinite(m->dhf[k]))
-            return fail(c, LBFD_E_INVAL, "bad species data");
-        h.M.push_back(m->M[k]);
-        h.dhf.push_back(m->dhf[k]);
-        h.mu_star.push_back(m->mu_star[k]);
-    }
-    for (int j = 0; j < nr; ++j) {
-        if (!(m->A[j] >= 0.0) || !std::isfinite(m->beta[j]) || !std::isfinite(m->theta[j]) ||
-            !std::isfinite(m->lnKc_a[j]) || !std::isfinite(m->lnKc_b[j]))
-            return fail(c, LBFD_E_INVAL, "bad rate data");
-        h.A.push_back(m->A[j]);
-        h.beta.push_back(m->beta[j]);
-        h.theta.push_back(m->theta[j]);
-        h.lnKc_a.push_back(m->lnKc_a[j]);
-        h.lnKc_b.push_back(m->lnKc_b[j]);
-        h.rev.push_back(m->reversible[j] ? 1 : 0);
-        int order_f = 0, order_r = 0;
-        for (int k = 0; k < ns; ++k) {
-            const int f = m->nu_f[j * ns + k], r = m->nu_r[j * ns + k];
-            if (f < 0 || f > 3 || r < 0 || r > 3)
-                return fail(c, LBFD_E_INVAL, "stoichiometric coefficients must be 0..3");
-            h.nu_f.push_back(f);
-            h.nu_r.push_back(r);
-            order_f += f;
-            order_r += r;
-        }
-        if (order_f > 4 || order_r > 4)
-            return fail(c, LBFD_E_INVAL, "reaction order of a side above 4");
-    }
-    lbfd_status st = set_device(c);
-    if (st) return st;
+    std::string msg;
+    lbfd_status st = mech_from_abi(m, h, msg);
+    if (st) return fail(c, st, msg);
+    if (c->have_params && (st = check_stable(c, c->params, &h))) return st;
+    if ((st = set_device(c))) return st;
     HostMech old = c->mech;
     bool had = c->have_mech;
     c->mech = h;
@@ -754,7 +932,11 @@ lbfd_status lbfd_set_params(lbfd_ctx* c, const lbfd_params* p) {
     }
     if (c->have_state && c->have_params && p->closed != c->params.closed)
         return fail(c, LBFD_E_STATE, "closing or opening the domain needs a new init_state");
-    lbfd_status st = set_device(c);
+    if (!(p->T_max >= 0.0) || !std::isfinite(p->T_max))
+        return fail(c, LBFD_E_INVAL, "T_max must be finite and >= 0");
+    lbfd_status st = check_stable(c, *p, c->have_mech ? &c->mech : nullptr);
+    if (st) return st;
+    st = set_device(c);
     if (st) return st;
     lbfd_params old = c->params;
     bool had = c->have_params;
@@ -774,12 +956,28 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
     if (c->ns > 0 && !Y) return fail(c, LBFD_E_INVAL, "Y required when n_species > 0");
     if (!c->have_phi || !ready_for_tables(c))
         return fail(c, LBFD_E_STATE, "phase field, params (and mechanism) must be set first");
-    for (size_t i = 0; i < c->N; ++i)
+    double tmin = INFINITY, tmax = 0.0;
+    for (size_t i = 0; i < c->N; ++i) {
         if (!(T[i] > 0.0) || !std::isfinite(T[i]))
             return fail(c, LBFD_E_INVAL, "temperature must be positive and finite");
+        tmin = std::min(tmin, T[i]);
+        tmax = std::max(tmax, T[i]);
+    }
+    {  // the stability rule over the initial state's temperatures too
+        lbfd_stability_report r;
+        std::string msg;
+        if (stability_eval(c->grid, c->params, c->have_mech ? &c->mech : nullptr, tmin, tmax, r,
+                           msg))
+            return fail(c, LBFD_E_INVAL, "initial state: " + msg);
+    }
     lbfd_status st = set_device(c);
     if (st) return st;
-    if ((st = upload_field(c, c->L.T0, T, c->N))) return st;
+    c->have_state = false;  // a failure below leaves no usable state
+    // the temperature planes of this state hold T - T_ref (FP32 mode: the
+    // solid temperature, fixed for the run; FP64 mode: 0)
+    c->T_ref = c->fp32 ? c->params.T_solid : 0.0;
+    if ((st = upload_tables(c))) return st;
+    if ((st = upload_field(c, c->L.T0, T, c->N, c->T_ref))) return st;
     if (c->ns > 0 && (st = upload_field(c, c->L.Y0, Y, (size_t)c->ns * c->N))) return st;
     if (c->nsm > c->ns) {  // padded species planes of the kernel's bucket
         const size_t off = (size_t)c->ns * c->N * elem(c), len = (size_t)(c->nsm - c->ns) * c->N * elem(c);
@@ -812,6 +1010,8 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
     c->cur = 0;
     c->odd = 0;
     c->steps = 0;
+    c->state_T[0] = tmin;
+    c->state_T[1] = tmax;
     if (c->params.closed) {  // P0 = P0_in for the initial state; its sum of M / T
         const Par<double> pd = build_par<double>(c);
         P0State q{};
@@ -876,9 +1076,14 @@ lbfd_status lbfd_set_p0_state(lbfd_ctx* c, const double* in) {
 lbfd_status lbfd_set_populations(lbfd_ctx* c, const double* g, const double* divu) {
     if (!c || !g) return LBFD_E_INVAL;
     if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
+    for (size_t i = 0; i < (size_t)c->Q * c->N; ++i)
+        if (!std::isfinite(g[i])) return fail(c, LBFD_E_INVAL, "non-finite population");
+    if (divu)
+        for (size_t i = 0; i < c->N; ++i)
+            if (!std::isfinite(divu[i])) return fail(c, LBFD_E_INVAL, "non-finite divergence");
     lbfd_status st = set_device(c);
     if (st) return st;
-    if ((st = upload_field(c, c->L.g, g, (size_t)c->Q * c->N))) return st;
+    if ((st = upload_field(c, c->L.g, g, (size_t)c->Q * c->N, 0.0, pop_scale(c)))) return st;
     if (divu && (st = upload_field(c, c->L.divu, divu, c->N))) return st;
     c->odd = 0;
     return LBFD_OK;
@@ -910,7 +1115,7 @@ lbfd_status lbfd_read(lbfd_ctx* c, int32_t field, int32_t comp, double* out) {
     const size_t N = c->N, s = elem(c);
     switch (field) {
     case LBFD_F_T:
-        return download_field(c, c->cur ? c->L.T1 : c->L.T0, out, N);
+        return download_field(c, c->cur ? c->L.T1 : c->L.T0, out, N, c->T_ref);
     case LBFD_F_Y:
         if (comp < 0 || comp >= c->ns) return fail(c, LBFD_E_INVAL, "species index");
         return download_field(c, (c->cur ? c->L.Y1 : c->L.Y0) + comp * N * s, out, N);
@@ -918,13 +1123,14 @@ lbfd_status lbfd_read(lbfd_ctx* c, int32_t field, int32_t comp, double* out) {
         return download_field(c, c->L.divu, out, N);
     case LBFD_F_POPULATIONS: {
         if (comp < 0 || comp >= c->Q) return fail(c, LBFD_E_INVAL, "population index");
-        if (!c->odd) return download_field(c, c->L.g + comp * N * s, out, N);
+        // (the populations are stored scaled: 36 g in FP32 mode)
+        if (!c->odd) return download_field(c, c->L.g + comp * N * s, out, N, 0.0, pop_scale(c));
         // swapped AA layout: natural g_i(x) sits in slot opp(i) of x - c_i, or
         // in the cell's own slot i when x - c_i is outside the domain
         std::vector<double> own(N), nb(N);
         const int i = comp, j = opp(comp);
-        if ((st = download_field(c, c->L.g + i * N * s, own.data(), N))) return st;
-        if ((st = download_field(c, c->L.g + j * N * s, nb.data(), N))) return st;
+        if ((st = download_field(c, c->L.g + i * N * s, own.data(), N, 0.0, pop_scale(c)))) return st;
+        if ((st = download_field(c, c->L.g + j * N * s, nb.data(), N, 0.0, pop_scale(c)))) return st;
         const int* cx = c->dim == 2 ? Lat<2>::cx : Lat<3>::cx;
         const int* cy = c->dim == 2 ? Lat<2>::cy : Lat<3>::cy;
         const int* cz = c->dim == 2 ? Lat<2>::cz : Lat<3>::cz;
@@ -1165,30 +1371,60 @@ lbfd_status lbfd_sample_states(lbfd_ctx* c, const int32_t* cells, int32_t n, flo
 }
 
 // ---------------------------------------------------------- halo planes
+// A slab of a decomposition along x holds one halo plane on each side (x = 0
+// and x = nx - 1) around its own planes 1 .. nx - 2.  What a neighbour needs
+// for the next step depends on the AA parity of the state:
+//  - T and Y_k of the slab's own boundary plane, for the neighbour's halo;
+//  - populations.  After an even (in-place) step the state is swapped: slot
+//    opp(i) of a cell holds its post-collision g_i, and the next (odd) step
+//    gathers the neighbour's from its halo cells: the own boundary plane's
+//    slots with c_x = -face go to the same slots of the neighbour's halo
+//    plane.  After an odd step the populations a slab pushed across the face
+//    sit in its halo plane, slots with c_x = face; they belong in the same
+//    slots of the neighbour's own boundary plane.
 extern "C++" {
 namespace {
 template <typename R>
-int halo_planes(lbfd_ctx* c, int dir, R** out) {
+int halo_planes(lbfd_ctx* c, int face, bool pack, R** out, int* xs) {
     const size_t N = c->N;
+    const int nx = c->grid.nx;
+    const int own = face < 0 ? 1 : nx - 2, halo = face < 0 ? 0 : nx - 1;
+    const bool swapped = c->odd != 0;  // the next step is odd
+    // populations: which plane and which slots
+    int pop_x, dir;
+    if (swapped) {
+        pop_x = pack ? own : halo;
+        dir = pack ? -face : face;
+    } else {
+        pop_x = pack ? halo : own;
+        dir = pack ? face : -face;
+    }
     R* g = dptr<R>(c, c->L.g);
     const int* cx = c->dim == 2 ? Lat<2>::cx : Lat<3>::cx;
     int n = 0;
     for (int i = 0; i < c->Q; ++i)
-        if (cx[i] == dir) out[n++] = g + (size_t)i * N;
+        if (cx[i] == dir) {
+            xs[n] = pop_x;
+            out[n++] = g + (size_t)i * N;
+        }
+    const int tx = pack ? own : halo;
+    xs[n] = tx;
     out[n++] = dptr<R>(c, c->cur ? c->L.T1 : c->L.T0);
     R* Y = dptr<R>(c, c->cur ? c->L.Y1 : c->L.Y0);
-    for (int k = 0; k < c->ns; ++k) out[n++] = Y + (size_t)k * N;
+    for (int k = 0; k < c->ns; ++k) {
+        xs[n] = tx;
+        out[n++] = Y + (size_t)k * N;
+    }
     return n;
 }
 template <typename R>
-lbfd_status halo_copy(lbfd_ctx* c, int x, int dir, void* buf, int pack) {
+lbfd_status halo_copy(lbfd_ctx* c, int face, void* buf, int pack) {
     HaloArgs<R> a;
     std::memset(&a, 0, sizeof(a));
-    a.nplanes = halo_planes<R>(c, dir, a.plane);
+    a.nplanes = halo_planes<R>(c, face, pack != 0, a.plane, a.xs);
     a.nx = c->grid.nx;
     a.ny = c->grid.ny;
     a.nz = c->grid.nz;
-    a.x = x;
     a.buf = reinterpret_cast<R*>(buf);
     a.pack = pack;
     hipError_t e;
@@ -1198,15 +1434,15 @@ lbfd_status halo_copy(lbfd_ctx* c, int x, int dir, void* buf, int pack) {
         e = launch_halo_f64(a, c->stream);
     return hip_check(c, e, "halo launch");
 }
-lbfd_status halo_entry(lbfd_ctx* c, int32_t x, int32_t dir, const void* buf, int pack) {
+lbfd_status halo_entry(lbfd_ctx* c, int32_t face, const void* buf, int pack) {
     if (!c || !buf) return LBFD_E_INVAL;
-    if (x < 0 || x >= c->grid.nx) return fail(c, LBFD_E_INVAL, "halo plane outside the grid");
-    if (dir != -1 && dir != 1) return fail(c, LBFD_E_INVAL, "halo direction must be -1 or +1");
+    if (face != -1 && face != 1) return fail(c, LBFD_E_INVAL, "halo face must be -1 or +1");
+    if (c->grid.nx < 3) return fail(c, LBFD_E_INVAL, "a slab needs nx >= 3 (two halo planes)");
     if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
     lbfd_status st = set_device(c);
     if (st) return st;
     void* b = const_cast<void*>(buf);
-    return c->fp32 ? halo_copy<float>(c, x, dir, b, pack) : halo_copy<double>(c, x, dir, b, pack);
+    return c->fp32 ? halo_copy<float>(c, face, b, pack) : halo_copy<double>(c, face, b, pack);
 }
 }  // namespace
 }  // extern "C++"
@@ -1218,12 +1454,12 @@ lbfd_status lbfd_halo_bytes(const lbfd_ctx* c, size_t* bytes) {
     return LBFD_OK;
 }
 
-lbfd_status lbfd_halo_pack(lbfd_ctx* c, int32_t x, int32_t dir, void* buf) {
-    return halo_entry(c, x, dir, buf, 1);
+lbfd_status lbfd_halo_pack(lbfd_ctx* c, int32_t face, void* buf) {
+    return halo_entry(c, face, buf, 1);
 }
 
-lbfd_status lbfd_halo_unpack(lbfd_ctx* c, int32_t x, int32_t dir, const void* buf) {
-    return halo_entry(c, x, dir, buf, 0);
+lbfd_status lbfd_halo_unpack(lbfd_ctx* c, int32_t face, const void* buf) {
+    return halo_entry(c, face, buf, 0);
 }
 
 lbfd_status lbfd_set_timing(lbfd_ctx* c, int32_t enable) {

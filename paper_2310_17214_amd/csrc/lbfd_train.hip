@@ -520,6 +520,26 @@ lbfd_status pack(lbfd_trainer* t) {
     return thip(t, hipGetLastError(), "pack");
 }
 
+// Statistics in the host layouts of lbfd_set_surrogate (either may be NULL).
+void norm_to_host(const TrainNorm& nm, int ni, int no, float* norm, float* env) {
+    if (norm) {
+        for (int i = 0; i < ni; ++i) {
+            norm[i] = nm.mu_x[i];
+            norm[ni + i] = nm.sd_x[i];
+        }
+        for (int o = 0; o < no; ++o) {
+            norm[2 * ni + o] = nm.mu_y[o];
+            norm[2 * ni + no + o] = nm.sd_y[o];
+        }
+    }
+    if (env) {
+        for (int i = 0; i < ni; ++i) {
+            env[i] = nm.lo[i];
+            env[ni + i] = nm.hi[i];
+        }
+    }
+}
+
 lbfd_status batch_args(lbfd_trainer* t, const float* x, const float* y, int32_t n,
                        const int32_t* idx) {
     if (!x || !y || !idx || n < 1) return tfail(t, LBFD_E_INVAL, "data and batch indices");
@@ -648,23 +668,7 @@ lbfd_status lbfd_trainer_export(lbfd_trainer* t, float* w, float* norm, float* e
                                      t->stream), "export")))
         return st;
     if ((st = thip(t, hipStreamSynchronize(t->stream), "export"))) return st;
-    const int ni = t->ni, no = t->no;
-    if (norm) {
-        for (int i = 0; i < ni; ++i) {
-            norm[i] = nm.mu_x[i];
-            norm[ni + i] = nm.sd_x[i];
-        }
-        for (int o = 0; o < no; ++o) {
-            norm[2 * ni + o] = nm.mu_y[o];
-            norm[2 * ni + no + o] = nm.sd_y[o];
-        }
-    }
-    if (env) {
-        for (int i = 0; i < ni; ++i) {
-            env[i] = nm.lo[i];
-            env[ni + i] = nm.hi[i];
-        }
-    }
+    norm_to_host(nm, t->ni, t->no, norm, env);
     return LBFD_OK;
 }
 

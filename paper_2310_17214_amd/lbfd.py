@@ -35,7 +35,7 @@ EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd
             "lbfd_trainer_workspace_bytes", "lbfd_trainer_create", "lbfd_trainer_fit_norm",
             "lbfd_trainer_set_weights", "lbfd_trainer_step", "lbfd_trainer_gradient",
             "lbfd_trainer_export", "lbfd_trainer_destroy", "lbfd_trainer_last_error",
-            "lbfd_destroy", "lbfd_last_error"]
+            "lbfd_destroy", "lbfd_last_error", "lbfd_stability"]
 LBFD_KERNEL_STEP, LBFD_KERNEL_ISLAND, LBFD_KERNEL_SURROGATE = 0, 1, 2
 
 
@@ -60,11 +60,18 @@ class Params(C.Structure):
                 ("Le", C.c_double * MAX_SPECIES),
                 ("fd_face", (C.c_double * (1 + MAX_SPECIES)) * 6),
                 ("n_sub", C.c_int32), ("ign_threshold", C.c_double),
-                ("closed", C.c_int32), ("r_gas", C.c_double)]
+                ("closed", C.c_int32), ("r_gas", C.c_double), ("T_max", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
+
+
+class StabilityReport(C.Structure):
+    _fields_ = [("T_lo", C.c_double), ("T_hi", C.c_double), ("tau_lo", C.c_double),
+                ("alpha_hi", C.c_double), ("D_hi", C.c_double), ("h_hi", C.c_double),
+                ("u_sum", C.c_double), ("fd_sum", C.c_double), ("kappa_hi", C.c_double),
+                ("h_kappa", C.c_double), ("violated", C.c_int32)]
 
 
 class Mechanism(C.Structure):
@@ -114,8 +121,8 @@ def lib():
         L.lbfd_surrogate_eval.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp]
         L.lbfd_sample_states.argtypes = [vp, vp, C.c_int32, vp, vp]
         L.lbfd_halo_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
-        L.lbfd_halo_pack.argtypes = [vp, C.c_int32, C.c_int32, vp]
-        L.lbfd_halo_unpack.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.lbfd_halo_pack.argtypes = [vp, C.c_int32, vp]
+        L.lbfd_halo_unpack.argtypes = [vp, C.c_int32, vp]
         L.lbfd_trainer_workspace_bytes.argtypes = [C.POINTER(TrainCfg), C.POINTER(C.c_size_t)]
         L.lbfd_trainer_create.argtypes = [C.POINTER(TrainCfg), vp, C.c_size_t, vp, C.POINTER(vp)]
         L.lbfd_trainer_fit_norm.argtypes = [vp, vp, vp, C.c_int32]
@@ -128,6 +135,8 @@ def lib():
         L.lbfd_trainer_last_error.restype = C.c_char_p
         L.lbfd_set_timing.argtypes = [vp, C.c_int32]
         L.lbfd_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), _dp]
+        L.lbfd_stability.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.POINTER(Mechanism),
+                                     C.c_double, C.c_double, C.POINTER(StabilityReport)]
         L.lbfd_destroy.argtypes = [vp]
         L.lbfd_last_error.argtypes = [vp]
         L.lbfd_last_error.restype = C.c_char_p
@@ -172,6 +181,7 @@ def make_params(s: dict) -> Params:
             p.fd_face[f][j] = v
     p.n_sub, p.ign_threshold = s["n_sub"], s["theta_ign"]
     p.closed, p.r_gas = int(s.get("closed", 0)), float(s.get("r_gas", 0.0))
+    p.T_max = float(s.get("T_max", 0.0))
     return p
 
 
@@ -197,6 +207,18 @@ class _MechArrays:
         for k, a in self.arrs.items():
             setattr(st, k, a.ctypes.data_as(_ip if a.dtype == np.int32 else _dp))
         self.struct = st
+
+
+def stability(setup: dict, T_lo=0.0, T_hi=0.0):
+    """The library's explicit-stability rule for a setup (host only, no
+    device): (status, report dict) with status LBFD_OK or LBFD_E_INVAL."""
+    g = make_grid(setup)
+    p = make_params(setup)
+    m = _MechArrays(setup) if setup["ns"] > 0 else None
+    r = StabilityReport()
+    st = lib().lbfd_stability(C.byref(g), C.byref(p), C.byref(m.struct) if m else None,
+                              float(T_lo), float(T_hi), C.byref(r))
+    return st, {k: getattr(r, k) for k, _ in StabilityReport._fields_}
 
 
 def _f64(a):
@@ -382,13 +404,15 @@ class Context:
             raise ValueError("halo buffer too small")
         return buf.data_ptr()
 
-    def halo_pack(self, x, direction, buf):
-        """Pack plane x, populations with c_x = direction, then T and Y_k."""
-        self._check(lib().lbfd_halo_pack(self._h, int(x), int(direction), self._halo_buf(buf)))
+    def halo_pack(self, face, buf):
+        """Pack what the neighbour on `face` (-1 left, +1 right) needs for the
+        next step into buf (populations for the state's AA parity, then T and
+        Y_k of the own boundary plane)."""
+        self._check(lib().lbfd_halo_pack(self._h, int(face), self._halo_buf(buf)))
 
-    def halo_unpack(self, x, direction, buf):
-        self._check(lib().lbfd_halo_unpack(self._h, int(x), int(direction),
-                                           self._halo_buf(buf)))
+    def halo_unpack(self, face, buf):
+        """Unpack a buffer the neighbour on `face` packed for this slab."""
+        self._check(lib().lbfd_halo_unpack(self._h, int(face), self._halo_buf(buf)))
 
     def set_timing(self, enable=True):
         self._check(lib().lbfd_set_timing(self._h, int(bool(enable))))

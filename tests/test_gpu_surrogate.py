@@ -31,6 +31,7 @@ def _crop9(precision="fp32", **kw):
     args.update(kw)
     wl = W.bed_superquadric_9sp(**args)
     wl.setup["theta_ign"] = 0.01
+    wl.setup["nu_in"] = 0.004  # within the stability rule at 1400 K
     return wl
 
 
