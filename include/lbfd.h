@@ -416,6 +416,21 @@ lbfd_status lbfd_trainer_gradient(lbfd_trainer* tr, const float* x, const float*
 lbfd_status lbfd_trainer_export(lbfd_trainer* tr, float* weights, float* norm, float* envelope);
 lbfd_status lbfd_trainer_destroy(lbfd_trainer* tr);
 
+/* The statistics of lbfd_trainer_fit_norm followed by lbfd_trainer_export's
+ * norm and envelope, without a trainer, a workspace or any allocation: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  x [n][2 + n_species] and
+ * y [n][n_species] are device arrays as written by lbfd_sample_states; norm
+ * (2 (2 + ns) + 2 ns floats) and envelope (2 (2 + ns) floats) are host
+ * arrays in lbfd_set_surrogate's layouts (either may be NULL, not both);
+ * hip_stream as in lbfd_create.  The kernel stages the statistics in a
+ * 4 KiB device array of the library (one per GPU, held until the process
+ * ends), which bounds n_species to 1..14 (LBFD_E_UNSUPPORTED beyond);
+ * LBFD_E_INVAL for n < 2 or null data.  Waits for the stream.  Calls on one
+ * GPU share that array: calls that overlap on one GPU (other threads or
+ * streams) race and must be serialised by the caller. */
+lbfd_status lbfd_fit_norm_noalloc(int32_t n_species, const float* x, const float* y, int32_t n,
+                                  float* norm, float* envelope, void* hip_stream);
 const char* lbfd_trainer_last_error(const lbfd_trainer* tr);
 
 /* ------------------------------------------------------------------------

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -540,6 +541,42 @@ void norm_to_host(const TrainNorm& nm, int ni, int no, float* norm, float* env) 
     }
 }
 
+// ------------------------------------------ statistics without allocation
+// The statistics kernel of lbfd_trainer_fit_norm writes into a device-side
+// staging block that, for lbfd_fit_norm_noalloc, is this file-scope array: one
+// copy per GPU, alive until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is a stand-in, not a
+// device address): it passes the address hipGetSymbolAddress returns for the
+// current device, looked up once per device and kept in scratch_addr.
+constexpr size_t NORM_SCRATCH_BYTES = 4096;  // one TrainNorm (16 inputs, 16 outputs)
+static_assert(sizeof(TrainNorm) <= NORM_SCRATCH_BYTES, "statistics scratch");
+static __device__ __align__(256) unsigned char scratch[NORM_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+void* scratch_addr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device); nullptr and the HIP error otherwise.
+void* scratch_for_device(int device, hipError_t* err) {
+    *err = hipSuccess;
+    if (device < 0 || device >= MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        scratch_addr[device] = p;
+    }
+    return scratch_addr[device];
+}
+
 lbfd_status batch_args(lbfd_trainer* t, const float* x, const float* y, int32_t n,
                        const int32_t* idx) {
     if (!x || !y || !idx || n < 1) return tfail(t, LBFD_E_INVAL, "data and batch indices");
@@ -669,6 +706,30 @@ lbfd_status lbfd_trainer_export(lbfd_trainer* t, float* w, float* norm, float* e
         return st;
     if ((st = thip(t, hipStreamSynchronize(t->stream), "export"))) return st;
     norm_to_host(nm, t->ni, t->no, norm, env);
+    return LBFD_OK;
+}
+
+lbfd_status lbfd_fit_norm_noalloc(int32_t n_species, const float* x, const float* y, int32_t n,
+                                  float* norm, float* envelope, void* hip_stream) {
+    if (n_species < 1 || 2 + n_species > MLP_KIN || n_species > MLP_OUT)
+        return LBFD_E_UNSUPPORTED;  // the staging block holds 16 inputs and 16 outputs
+    if (!x || !y || n < 2 || (!norm && !envelope)) return LBFD_E_INVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return LBFD_E_DEVICE;
+    hipError_t e;
+    TrainNorm* d = static_cast<TrainNorm*>(scratch_for_device(dev, &e));
+    if (!d) return LBFD_E_DEVICE;
+    const hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const int ni = 2 + n_species, no = n_species;
+    // every field the outputs use is written by the kernel (one workgroup per
+    // column), so nothing from an earlier call survives into this one
+    hipLaunchKernelGGL(norm_fit_kernel, dim3(ni + no), dim3(TB), 0, s, x, y, n, ni, no, d);
+    if (hipGetLastError() != hipSuccess) return LBFD_E_DEVICE;
+    TrainNorm nm;
+    if (hipMemcpyAsync(&nm, d, sizeof(nm), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return LBFD_E_DEVICE;
+    norm_to_host(nm, ni, no, norm, envelope);
     return LBFD_OK;
 }
 

@@ -35,7 +35,7 @@ EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd
             "lbfd_trainer_workspace_bytes", "lbfd_trainer_create", "lbfd_trainer_fit_norm",
             "lbfd_trainer_set_weights", "lbfd_trainer_step", "lbfd_trainer_gradient",
             "lbfd_trainer_export", "lbfd_trainer_destroy", "lbfd_trainer_last_error",
-            "lbfd_destroy", "lbfd_last_error", "lbfd_stability"]
+            "lbfd_destroy", "lbfd_last_error", "lbfd_stability", "lbfd_fit_norm_noalloc"]
 LBFD_KERNEL_STEP, LBFD_KERNEL_ISLAND, LBFD_KERNEL_SURROGATE = 0, 1, 2
 
 
@@ -137,6 +137,7 @@ def lib():
         L.lbfd_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), _dp]
         L.lbfd_stability.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.POINTER(Mechanism),
                                      C.c_double, C.c_double, C.POINTER(StabilityReport)]
+        L.lbfd_fit_norm_noalloc.argtypes = [C.c_int32, vp, vp, C.c_int32, _fp, _fp, vp]
         L.lbfd_destroy.argtypes = [vp]
         L.lbfd_last_error.argtypes = [vp]
         L.lbfd_last_error.restype = C.c_char_p
@@ -207,6 +208,26 @@ class _MechArrays:
         for k, a in self.arrs.items():
             setattr(st, k, a.ctypes.data_as(_ip if a.dtype == np.int32 else _dp))
         self.struct = st
+
+
+def fit_norm_noalloc(n_species, x, y, stream=None):
+    """Normalisation statistics and envelope of training pairs (torch float32
+    CUDA tensors x [n, 2 + ns], y [n, ns]) through the entry point that
+    allocates nothing: (norm, envelope) as numpy float32 arrays."""
+    import torch
+
+    ni = 2 + n_species
+    x, y = x.contiguous(), y.contiguous()
+    nrm = np.empty(2 * ni + 2 * n_species, np.float32)
+    env = np.empty(2 * ni, np.float32)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    fp = C.POINTER(C.c_float)
+    st = lib().lbfd_fit_norm_noalloc(int(n_species), x.data_ptr(), y.data_ptr(), int(x.shape[0]),
+                                     nrm.ctypes.data_as(fp), env.ctypes.data_as(fp),
+                                     C.c_void_p(s.cuda_stream))
+    if st != LBFD_OK:
+        raise LbfdError(st, "fit_norm_noalloc")
+    return nrm, env
 
 
 def stability(setup: dict, T_lo=0.0, T_hi=0.0):
