@@ -59,6 +59,7 @@ struct orc_ctx {
     int corr;                       /* species correction flux needed (unequal Le) */
     double *phi, *g, *gs, *T, *Y, *divu;
     double *u, *Ph, *rho_n, *Tst, *Yst, *qT;
+    double* uprof;                  /* inlet velocity per row [3][ny*nz], or NULL */
     double diag[ORC_D_LEN];
     double p_prev, S0;               /* closed domain: previous P0 / P0_in, and the
                                         sum of M / T of the initial state        */
@@ -66,6 +67,24 @@ struct orc_ctx {
 
 static long cidx(const orc_ctx* o, int x, int y, int z) {
     return ((long)z * o->s.ny + y) * o->s.nx + x;
+}
+
+/* Sharp-interface reference mode (Sec. 4): the bulk phases are separated at
+ * phi = 1/2, so a cell with phi_s >= 1/2 is solid. */
+static int is_solid(const orc_ctx* o, long id) { return o->s.si && o->phi[id] >= 0.5; }
+
+/* The in-domain cell (x, y, z) after periodic wrapping is solid (0 when it
+ * lies beyond a non-periodic face). */
+static int solid_at(const orc_ctx* o, int x, int y, int z) {
+    const orc_setup* s = &o->s;
+    if (!s->si) return 0;
+    int p[3] = {x, y, z}, n[3] = {s->nx, s->ny, s->nz};
+    for (int a = 0; a < 3; ++a) {
+        if (p[a] >= 0 && p[a] < n[a]) continue;
+        if (s->fd_bc[2 * a + (p[a] < 0 ? 0 : 1)] != ORC_FD_PERIODIC) return 0;
+        p[a] = (p[a] + n[a]) % n[a];
+    }
+    return is_solid(o, cidx(o, p[0], p[1], p[2]));
 }
 
 /* ---------------------------------------------------------------- closures */
@@ -233,6 +252,7 @@ static void lb_macro(const orc_ctx* o, const double* gb, double rho, double mu, 
     }
     double phif = 1.0 - phis;
     double K = s->A_u * mu * phif * phis * phis / (s->eta * s->eta);
+    if (s->si) K = 0.0; /* SI mode: no interface drag */
     for (int a = 0; a < 3; ++a) {
         m[a] = m[a] / CS2;
         u[a] = (m[a] + 0.5 * s->F_b[a]) / (rho + 0.5 * K);
@@ -246,7 +266,12 @@ static void lb_macro(const orc_ctx* o, const double* gb, double rho, double mu, 
 /* State (T, Y) at an in-domain cell or at a ghost one step outside a face.
  * Periodic faces wrap; Dirichlet ghosts carry the face value (cell-centred
  * ghost); zero-gradient ghosts copy the cell on the inside (the caller's
- * cell, which is the only in-domain neighbour of a ghost on one axis).       */
+ * cell, which is the only in-domain neighbour of a ghost on one axis).
+ * Sharp-interface mode: a solid cell seen from a fluid cell is a ghost that
+ * holds the solid temperature T_s at its centre (a fixed-temperature wall
+ * for conduction) and the fluid cell's own composition (no species flux
+ * into the solid); every term that reads the neighbour (diffusion,
+ * convection, the density gradient) sees that ghost.                         */
 static void state_at(const orc_ctx* o, int x, int y, int z, int cx, int cy, int cz, double* T,
                      double* Y) {
     const orc_setup* s = &o->s;
@@ -269,6 +294,12 @@ static void state_at(const orc_ctx* o, int x, int y, int z, int cx, int cy, int 
         }
     }
     long id = cidx(o, p[0], p[1], p[2]);
+    if (is_solid(o, id)) {
+        long ic = cidx(o, cc[0], cc[1], cc[2]);
+        *T = s->T_s;
+        for (int k = 0; k < s->ns; ++k) Y[k] = o->Y[(long)k * o->N + ic];
+        return;
+    }
     *T = o->T[id];
     for (int k = 0; k < s->ns; ++k) Y[k] = o->Y[(long)k * o->N + id];
 }
@@ -304,6 +335,13 @@ static void lb_collide_phase(orc_ctx* o) {
                 double Yc[ORC_MAXS];
                 for (int k = 0; k < s->ns; ++k) Yc[k] = o->Y[(long)k * o->N + id];
                 double rho = orc_eos(s, o->T[id], Yc);
+                if (is_solid(o, id)) { /* SI mode: a solid cell holds no flow */
+                    for (int i = 0; i < o->Q; ++i) o->gs[(long)i * o->N + id] = o->g[(long)i * o->N + id];
+                    for (int a = 0; a < 3; ++a) o->u[(long)a * o->N + id] = 0.0;
+                    o->Ph[id] = 0.0;
+                    o->rho_n[id] = rho;
+                    continue;
+                }
                 mixture(s, o->Phi, o->T[id], Yc, &mu, &lam, NULL);
                 for (int i = 0; i < o->Q; ++i) gb[i] = o->g[(long)i * o->N + id];
                 grad_rho(o, x, y, z, G);
@@ -337,9 +375,14 @@ static void lb_stream_phase(orc_ctx* o) {
         for (int y = 0; y < s->ny; ++y)
             for (int x = 0; x < s->nx; ++x) {
                 long id = cidx(o, x, y, z);
+                if (is_solid(o, id)) { /* SI mode: nothing streams in a solid cell */
+                    for (int i = 0; i < o->Q; ++i) o->g[(long)i * o->N + id] = o->gs[(long)i * o->N + id];
+                    continue;
+                }
                 for (int i = 0; i < o->Q; ++i) {
                     int p[3] = {x - o->c[i][0], y - o->c[i][1], z - o->c[i][2]};
-                    int wall = 0, inlet = 0, outlet = 0;
+                    /* SI mode: a link to a solid cell is a halfway bounce-back wall */
+                    int wall = solid_at(o, p[0], p[1], p[2]), inlet = 0, outlet = 0;
                     for (int a = 0; a < 3; ++a) {
                         if (p[a] >= 0 && p[a] < n[a]) continue;
                         int face = 2 * a + (p[a] < 0 ? 0 : 1);
@@ -359,7 +402,11 @@ static void lb_stream_phase(orc_ctx* o) {
                     } else if (inlet || outlet) {
                         double ub[3], ph, rho, geq[19];
                         if (inlet) {
-                            for (int a = 0; a < 3; ++a) ub[a] = s->u_in[a];
+                            /* inlet velocity of this row (y, z): the profile if
+                             * one is set, else the uniform u_in */
+                            long r = (long)z * s->ny + y;
+                            for (int a = 0; a < 3; ++a)
+                                ub[a] = o->uprof ? o->uprof[(long)a * s->ny * s->nz + r] : s->u_in[a];
                             if (s->dim == 2) ub[2] = 0.0;
                             ph = o->Ph[id];
                             rho = s->rho_in;
@@ -407,6 +454,7 @@ static void fd_cell(const orc_ctx* o, int x, int y, int z, const double* u, doub
     mixture(s, o->Phi, Tc, Yc, &mu_c, &lam_c, rD_c);
     double phis = o->phi[id], phif = 1.0 - phis;
     double H = s->A_T * lam_c * phif * phis * phis / (s->eta * s->eta);
+    if (s->si) H = 0.0; /* SI mode: no interface heat exchange */
 
     double advT = 0.0, lapT = 0.0, advY[ORC_MAXS], J[ORC_MAXS];
     for (int k = 0; k < ns; ++k) advY[k] = J[k] = 0.0;
@@ -461,6 +509,13 @@ static void fd_phase(orc_ctx* o, int zero_u) {
             for (int x = 0; x < s->nx; ++x) {
                 long id = cidx(o, x, y, z);
                 double u[3] = {0.0, 0.0, 0.0}, Y[ORC_MAXS], T, q;
+                if (is_solid(o, id)) { /* SI mode: the solid keeps its state */
+                    o->Tst[id] = o->T[id];
+                    for (int k = 0; k < s->ns; ++k)
+                        o->Yst[(long)k * o->N + id] = o->Y[(long)k * o->N + id];
+                    o->qT[id] = 0.0;
+                    continue;
+                }
                 if (!zero_u)
                     for (int a = 0; a < s->dim; ++a) u[a] = o->u[(long)a * o->N + id];
                 fd_cell(o, x, y, z, u, &T, Y, &q);
@@ -534,7 +589,7 @@ static void chem_phase(orc_ctx* o, int do_chem) {
     for (long id = 0; id < o->N; ++id) {
         double T = o->Tst[id], Y[ORC_MAXS], T0 = T;
         for (int k = 0; k < s->ns; ++k) Y[k] = o->Yst[(long)k * o->N + id];
-        if (do_chem && s->ns > 0 && s->nr > 0) {
+        if (do_chem && s->ns > 0 && s->nr > 0 && !is_solid(o, id)) {
             double wk[ORC_MAXS], wT, rho = orc_eos(s, T, Y);
             rates(s, T, Y, rho, wk, &wT);
             if (fabs(wT) / (rho * s->cp) > s->theta_ign) flagged++;
@@ -642,6 +697,7 @@ void orc_destroy(orc_ctx* o) {
     if (!o) return;
     free(o->phi); free(o->g); free(o->gs); free(o->T); free(o->Y); free(o->divu);
     free(o->u); free(o->Ph); free(o->rho_n); free(o->Tst); free(o->Yst); free(o->qT);
+    free(o->uprof);
     free(o);
 }
 
@@ -668,6 +724,18 @@ int orc_init_state(orc_ctx* o, const double* T, const double* Y, const double* u
     for (int k = 0; k < ORC_D_LEN; ++k) o->diag[k] = 0.0;
     reduce_phase(o, 0); /* snapshot sums of the initial state; counters start at zero */
     o->S0 = s->closed ? closed_sum(o) : 0.0;
+    return 0;
+}
+
+int orc_set_inlet_profile(orc_ctx* o, const double* u) {
+    const orc_setup* s = &o->s;
+    long nr = (long)s->ny * s->nz;
+    free(o->uprof);
+    o->uprof = NULL;
+    if (!u) return 0;
+    o->uprof = (double*)calloc(3 * nr, sizeof(double));
+    for (int a = 0; a < s->dim; ++a)
+        for (long r = 0; r < nr; ++r) o->uprof[a * nr + r] = u[a * nr + r];
     return 0;
 }
 
@@ -749,6 +817,10 @@ int orc_read(const orc_ctx* o, int32_t field, int32_t comp, double* out) {
                     double rho = orc_eos(s, o->T[id], Yc);
                     if (field == ORC_F_RHO) {
                         out[id] = rho;
+                        continue;
+                    }
+                    if (is_solid(o, id)) { /* SI mode: a solid cell is at rest */
+                        out[id] = 0.0;
                         continue;
                     }
                     mixture(s, o->Phi, o->T[id], Yc, &mu, &lam, NULL);

@@ -62,6 +62,12 @@ typedef struct {
     int32_t closed;
     double  r_gas;                    /* R / M_ref in the units of cp            */
     double  p0;                       /* P0 / P0_in, kept by the oracle          */
+    /* sharp-interface reference mode (Sec. 4: the phase-field coupling switched
+     * off, bulk phases separated at phi = 1/2): cells with phi_s >= 1/2 are
+     * solid -- halfway bounce-back for the populations, a ghost at T_s for
+     * heat conduction, no species or advective flux -- and the drag and
+     * heat-exchange terms vanish.  0: the diffuse-interface model */
+    int32_t si;
 } orc_setup;
 
 typedef struct orc_ctx orc_ctx;
@@ -73,6 +79,9 @@ int      orc_init_state(orc_ctx* o, const double* T, const double* Y, const doub
 /* overwrite the post-stream populations (Q*N, natural layout) and, if not
  * NULL, the thermal divergence (N) -- restores a saved state */
 int      orc_set_populations(orc_ctx* o, const double* g, const double* divu);
+/* velocity inlet profile: u[a][z*ny + y] for a < dim (the inlet velocity of
+ * each row of the -x face); NULL returns to the uniform u_in */
+int      orc_set_inlet_profile(orc_ctx* o, const double* u);
 int      orc_step(orc_ctx* o, int32_t n, int32_t phase_mask);
 int      orc_read(const orc_ctx* o, int32_t field, int32_t comp, double* out);
 void     orc_diag(const orc_ctx* o, double* out /* ORC_D_LEN */);

@@ -44,6 +44,7 @@ class Setup(C.Structure):
         ("A", C.c_double * MAXR), ("beta", C.c_double * MAXR), ("theta", C.c_double * MAXR),
         ("rev", C.c_int32 * MAXR), ("lnKc_a", C.c_double * MAXR), ("lnKc_b", C.c_double * MAXR),
         ("closed", C.c_int32), ("r_gas", C.c_double), ("p0", C.c_double),
+        ("si", C.c_int32),
     ]
 
 
@@ -70,6 +71,7 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_init_state.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_set_populations.argtypes = [C.c_void_p, dp, dp]
+        L.orc_set_inlet_profile.argtypes = [C.c_void_p, dp]
         L.orc_step.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.orc_read.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp]
         L.orc_diag.argtypes = [C.c_void_p, dp]
@@ -127,6 +129,7 @@ def make_setup(s: dict) -> Setup:
     st.closed = int(s.get("closed", 0))
     st.r_gas = float(s.get("r_gas", 0.0))
     st.p0 = 1.0
+    st.si = int(s.get("si", 0))
     return st
 
 
@@ -162,6 +165,16 @@ class Oracle:
         assert g.size == self.Q * self.N
         d = None if divu is None else np.ascontiguousarray(divu, dtype=np.float64).reshape(-1)
         lib().orc_set_populations(self._h, _dp(g), None if d is None else _dp(d))
+
+    def set_inlet_profile(self, u):
+        """Velocity of each inlet row, u[a][z][y] for a < dim (None: uniform u_in)."""
+        if u is None:
+            lib().orc_set_inlet_profile(self._h, None)
+            return
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+        assert u.size == self.dim * self.shape[0] * self.shape[1]
+        self._uprof = u
+        lib().orc_set_inlet_profile(self._h, _dp(u))
 
     def step(self, n=1, mask=PH_ALL):
         lib().orc_step(self._h, int(n), int(mask))

@@ -808,3 +808,165 @@ def test_first_order_upwind_on_a_quadratic_field():
     assert np.abs(Y1[inner] - refY).max() <= 1e-14
     # the step did advect (not a trivial fixed point)
     assert np.abs(T1[inner] - T0[inner]).min() > 1e-4
+
+
+# ------------------------------------------- sharp-interface reference mode
+
+def _si_poiseuille(ny, tau, umax, steps, phi_fluid):
+    """Channel between two solid rows of a y-periodic box (SI mode, Sec. 4):
+    rows 0 and ny + 1 have phi_s >= 1/2, the ny rows between them are fluid
+    and carry the phase-field values phi_fluid (< 1/2)."""
+    s, mu, Fb = _channel(ny, tau, umax)
+    s["lb_bc"] = ["periodic"] * 6
+    s["fd_bc"] = ["periodic"] * 6
+    s["ny"] = ny + 2
+    s["si"] = 1
+    s["A_u"], s["A_T"] = 145.0, 70.0
+    shape = (1, ny + 2, s["nx"])
+    phi = np.empty(shape)
+    phi[0, 1:-1, :] = np.asarray(phi_fluid)[:, None]
+    phi[0, 0, :] = 0.5   # the threshold itself is solid
+    phi[0, -1, :] = 1.0
+    o = O.Oracle(s, phi)
+    o.init_state(np.full(shape, 300.0))
+    o.step(steps)
+    u = o.fields()["u"][0][0, :, 0]
+    xi = (np.arange(ny) + 0.5) / ny
+    Um = Fb * ny ** 2 / (12.0 * mu)
+    return u, 6.0 * Um * xi * (1 - xi)
+
+
+def test_si_poiseuille_between_solid_rows_is_exact_at_magic_tau():
+    """SI mode: cells with phi_s >= 1/2 are halfway bounce-back walls and the
+    coupling terms are switched off, so a channel of solid rows reproduces
+    the analytic profile (the P5 setting) although its fluid cells carry
+    phase-field values up to 0.45 with A_u = 145: with the coupling on, the
+    drag K = A_u mu phi_f phi_s^2/eta^2 of those cells would slow the flow.
+    The solid rows themselves report u = 0."""
+    ny = 16
+    phi_fluid = 0.45 * np.abs(np.sin(np.arange(ny) * 1.3))
+    u, ref = _si_poiseuille(ny, 0.5 + math.sqrt(3.0) / 4.0, 1e-3, 6000, phi_fluid)
+    assert rel(u[1:-1], ref) <= 1e-4
+    assert u[0] == 0.0 and u[-1] == 0.0
+
+
+def test_si_wall_is_halfway_between_solid_and_fluid_centres():
+    """Away from the magic tau the SI channel converges at second order to
+    the profile whose walls lie half a cell outside the fluid rows (a wall
+    at the solid cell's centre would leave a first-order error)."""
+    errs = []
+    for ny in (8, 16):
+        u, ref = _si_poiseuille(ny, 0.8, 1e-3, int(12 * ny ** 2 / 0.1), np.zeros(ny))
+        errs.append(rel(u[1:-1], ref))
+    assert errs[1] < errs[0] / 3.5, errs
+
+
+def test_si_conduction_to_a_solid_at_fixed_temperature():
+    """SI mode: a fluid cell next to a solid one sees a ghost at T_s on the
+    solid cell's centre.  With constant conductivity, the solid cells 0, 1
+    at T_s and a Dirichlet face temperature T_R past the last cell, the
+    steady state is the line through (1, T_s) and (nx, T_R) -- an exact
+    discrete fixed point of the central diffusion -- whatever A_T and the
+    fluid cells' phase field (the exchange term is off)."""
+    nx = 12
+    s = W.base_setup(2, nx, 1, 1, 0)
+    s["lb_bc"] = ["wall", "wall", "periodic", "periodic", "periodic", "periodic"]
+    s["fd_bc"] = ["neumann", "dirichlet", "periodic", "periodic", "periodic", "periodic"]
+    Ts, TR = 420.0, 300.0
+    s["T_s"] = Ts
+    s["fd_val"][1] = [TR]
+    s["mu_model"] = 0
+    s["nu_in"] = 0.1
+    s["si"] = 1
+    s["A_T"] = 500.0
+    shape = (1, 1, nx)
+    phi = np.full(shape, 0.3)
+    phi[0, 0, :2] = [1.0, 0.5]
+    o = O.Oracle(s, phi)
+    T0 = np.full(shape, 350.0)
+    T0[0, 0, :2] = Ts
+    o.init_state(T0)
+    o.step(15000)
+    T = o.read(O.F_T)[0, 0]
+    x = np.arange(nx)
+    ref = Ts + (TR - Ts) * (x - 1) / (nx - 1)
+    assert np.abs(T[2:] - ref[2:]).max() <= 1e-10 * Ts
+    assert T[0] == Ts and T[1] == Ts
+
+
+def test_si_species_stay_in_the_fluid_and_the_solid_is_untouched():
+    """SI mode, isothermal periodic box with a solid block: no species flux
+    enters the solid (its ghost carries the fluid cell's composition), so
+    with every molar mass 1 (rho independent of Y) the species masses of
+    the fluid cells are conserved to round-off; the solid cells' state and
+    populations never change, and no reaction runs there."""
+    s = _box(2, 12, ns=4, si=1, A_T=70.0)
+    s["nx"], s["ny"] = 12, 10
+    s["mech"] = W.mech_one_step(A=W.one_step_rate_constant(tau_steps=500.0))
+    s["Y_in"] = W.ONE_STEP_Y_IN
+    s["T_s"] = 1000.0
+    shape = (1, 10, 12)
+    phi = np.zeros(shape)
+    phi[0, 3:7, 4:9] = 1.0
+    solid = phi >= 0.5
+    rng = np.random.default_rng(4)
+    Y = rng.random((4,) + shape) + 0.1
+    Y /= Y.sum(0)
+    T0 = np.full(shape, 1000.0)
+    o = O.Oracle(s, phi)
+    o.init_state(T0, Y)
+    g0 = o.populations()
+    rho0 = o.read(O.F_RHO)
+    m0 = [(rho0 * Y[k])[~solid].sum() for k in range(4)]
+    # reaction off: species move by diffusion only
+    o.step(200, O.PH_LB | O.PH_FD)
+    f = o.fields()
+    m1 = [(f["rho"] * f["Y"][k])[~solid].sum() for k in range(4)]
+    assert np.allclose(m1, m0, rtol=0, atol=1e-13 * sum(m0))
+    assert np.array_equal(f["Y"][:, solid], Y[:, solid])
+    assert np.array_equal(o.populations()[:, solid], g0[:, solid])
+    assert np.abs(f["u"][:, solid]).max() == 0.0
+    # with the reaction on, the solid cells still keep their composition
+    o.step(50)
+    f = o.fields()
+    assert np.array_equal(f["Y"][:, solid], Y[:, solid])
+    assert np.array_equal(f["T"][solid], T0[solid])
+    assert np.abs(f["Y"][2][~solid] - Y[2][~solid]).max() > 1e-3  # products formed
+
+
+def test_inlet_profile_matches_uniform_inlet_and_shapes_the_flow():
+    """The per-row velocity inlet with every row at u_in reproduces the
+    uniform inlet exactly; a parabolic profile fixes the first column's
+    inflow to that parabola (its mean flux enters the channel)."""
+    ny = 10
+    s = W.base_setup(2, 24, ny, 1, 0)
+    s["lb_bc"] = ["inlet", "outlet", "wall", "wall", "periodic", "periodic"]
+    s["fd_bc"] = ["dirichlet", "neumann", "neumann", "neumann", "periodic", "periodic"]
+    s["fd_val"][0] = [300.0]
+    s["u_in"] = [0.02, 0.0, 0.0]
+    s["mu_model"] = 0
+    shape = (1, ny, 24)
+    a = O.Oracle(s, np.zeros(shape))
+    b = O.Oracle(s, np.zeros(shape))
+    a.init_state(np.full(shape, 300.0))
+    b.init_state(np.full(shape, 300.0))
+    prof = np.zeros((2, 1, ny))
+    prof[0] = 0.02
+    b.set_inlet_profile(prof)
+    a.step(50)
+    b.step(50)
+    assert np.array_equal(a.populations(), b.populations())
+    y = (np.arange(ny) + 0.5) / ny
+    prof[0, 0] = 0.03 * 4 * y * (1 - y)
+    c = O.Oracle(s, np.zeros(shape))
+    c.init_state(np.full(shape, 300.0))
+    c.set_inlet_profile(prof)
+    c.step(3000)
+    ux = c.fields()["u"][0][0]
+    # away from the wall rows (where the walls' bounce-back wins at the
+    # corner links) the first column follows the parabola
+    assert rel(ux[2:-2, 0], prof[0, 0, 2:-2]) < 0.03
+    # steady: one volume flux through every column, close to the profile's
+    flux = ux.sum(0)
+    assert np.abs(flux - flux[0]).max() < 1e-3 * flux[0]
+    assert abs(flux[0] / prof[0, 0].sum() - 1.0) < 0.02
