@@ -128,6 +128,20 @@ typedef struct {
                                         Dirichlet face temperatures and, from
                                         lbfd_init_state on, the initial state's
                                         maximum.  0: no bound beyond those           */
+    int32_t sharp_interface;         /* 1: sharp-interface reference mode (Sec. 4: the
+                                        coupling to the phase field switched off, the
+                                        bulk phases separated at phi = 1/2).  Cells
+                                        with phi >= 1/2 are solid: they keep their
+                                        state and populations and report u = 0,
+                                        P_h = 0; a fluid cell bounces its populations
+                                        back (halfway) at links to them and sees a
+                                        solid neighbour as a ghost cell at T_solid
+                                        with the fluid cell's own composition (in
+                                        diffusion, convection and the density
+                                        gradient); the drag and heat-exchange terms
+                                        vanish.  Up to 4 species, exact reaction step
+                                        only (no surrogate), no halo exchange.
+                                        0: the diffuse-interface model               */
 } lbfd_params;
 
 typedef struct {
@@ -282,6 +296,14 @@ lbfd_status lbfd_init_state(lbfd_ctx* ctx, const double* T, const double* Y, con
  * lbfd_init_state this restores a checkpoint written with lbfd_read.
  * LBFD_E_INVAL for non-finite values; LBFD_E_STATE before lbfd_init_state. */
 lbfd_status lbfd_set_populations(lbfd_ctx* ctx, const double* g, const double* divu);
+
+/* Velocity inlet profile (Sec. 4.2 imposes a fully developed parabolic inflow):
+ * u[a][z*ny + y] for a < dim, host memory, copied; the inlet row (y, z) of the
+ * -x face then takes the equilibrium at (rho_in, u(y, z), local P_h) instead
+ * of the uniform u_in of the params.  NULL returns to the uniform inlet.
+ * LBFD_E_INVAL when the -x face is no velocity inlet, for non-finite values
+ * or for |u| > 0.1 (the low-Mach limit). */
+lbfd_status lbfd_set_inlet_profile(lbfd_ctx* ctx, const double* u);
 
 /* Closed domain (Sec. 3.1): the thermodynamic-pressure state that a checkpoint
  * needs besides the fields: out/in[3] = {S0, p, p_prev}, the sum of M/T over

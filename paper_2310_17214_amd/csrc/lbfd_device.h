@@ -112,6 +112,20 @@ template <> struct Lat<3> {
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 };
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// Direction of the FD face f (2 axis + side, side 0 = minus): the axis
+// directions come first in both lattices, +axis then -axis.
+__host__ __device__ constexpr int face_dir(int f) { return (f ^ 1) + 1; }
+static_assert(Lat<3>::cx[face_dir(0)] == -1 && Lat<3>::cx[face_dir(1)] == 1 &&
+                  Lat<3>::cy[face_dir(2)] == -1 && Lat<3>::cy[face_dir(3)] == 1 &&
+                  Lat<3>::cz[face_dir(4)] == -1 && Lat<3>::cz[face_dir(5)] == 1 &&
+                  Lat<2>::cx[face_dir(0)] == -1 && Lat<2>::cy[face_dir(3)] == 1,
+              "face directions");
+
+// Sharp-interface mode: per-cell link mask.  Bit i (1 <= i < Q) is set when
+// the cell x + c_i (after periodic wrapping; none beyond a non-periodic face)
+// is solid, bit SI_SELF when the cell itself is.  A cell is solid when its
+// phase field is at least 1/2 (decided on the host in FP64).
+constexpr uint32_t SI_SELF = 1u << 31;
 
 // Stored populations = scale * g: 36 in FP32 mode, 1 in FP64 mode.
 template <typename R>
@@ -376,6 +390,9 @@ struct StepArgs {
     R* Y_nxt;             // [ns][N]
     R* divu;              // [N] (read, then overwritten in place)
     const R* phi;         // [N] solid fraction
+    const uint32_t* smask;     // [N] sharp-interface link masks (SI kernels only)
+    const double* inlet_prof;  // [ny*nz][19] rho_in c_s^2 e_j(u_in(y, z)) per inlet row,
+                               // or null: the uniform inlet_eq of the parameters
     double* partials;     // [nblocks][DIAG_STRIDE]
     unsigned long long* flags;  // [nblocks][zc][waves] reaction-active cells (FP32 mode)
     const Par<R>* P;
@@ -423,6 +440,7 @@ struct MacroArgs {
     const R* Y;
     const R* divu;
     const R* phi;
+    const uint32_t* smask;  // sharp-interface link masks, or null
     double* out;          // [5][N]: rho, u_x, u_y, u_z, P_h
     const Par<R>* P;
     const Par<double>* PD;

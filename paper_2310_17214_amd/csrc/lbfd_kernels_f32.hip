@@ -81,6 +81,10 @@ hipError_t launch_sample_f32(int nsm, const float* T, const float* Y, int N, con
     default: return hipErrorInvalidValue;
     }
 }
+hipError_t launch_si_mask_f32(int dim, const uint8_t* solid, const Par<float>* P, uint32_t* mask,
+                                int n, hipStream_t s) {
+    return launch_si_mask_t<float>(dim, solid, P, mask, n, s);
+}
 hipError_t launch_halo_f32(const HaloArgs<float>& a, hipStream_t s) {
     return launch_halo_t<float>(a, s);
 }

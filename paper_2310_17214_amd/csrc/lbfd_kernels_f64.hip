@@ -42,6 +42,10 @@ int step_tile_h_f64(int dim, int nsm) {
     default: return tile_h_t<double, 16>(dim);
     }
 }
+hipError_t launch_si_mask_f64(int dim, const uint8_t* solid, const Par<double>* P, uint32_t* mask,
+                                int n, hipStream_t s) {
+    return launch_si_mask_t<double>(dim, solid, P, mask, n, s);
+}
 hipError_t launch_halo_f64(const HaloArgs<double>& a, hipStream_t s) {
     return launch_halo_t<double>(a, s);
 }

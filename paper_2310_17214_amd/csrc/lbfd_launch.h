@@ -29,6 +29,11 @@ hipError_t launch_p0_sum_f32(const float* T, const float* Y, int N, int ns, cons
                              double* part, hipStream_t s);
 hipError_t launch_p0_sum_f64(const double* T, const double* Y, int N, int ns,
                              const Par<double>* P, double* part, hipStream_t s);
+// sharp-interface mode: link masks from the per-cell solid flags
+hipError_t launch_si_mask_f32(int dim, const uint8_t* solid, const Par<float>* P, uint32_t* mask,
+                              int n, hipStream_t s);
+hipError_t launch_si_mask_f64(int dim, const uint8_t* solid, const Par<double>* P, uint32_t* mask,
+                              int n, hipStream_t s);
 // halo planes of an x face
 hipError_t launch_halo_f32(const HaloArgs<float>& a, hipStream_t s);
 hipError_t launch_halo_f64(const HaloArgs<double>& a, hipStream_t s);

@@ -32,7 +32,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
     size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, gtot, list, count, p0, p0part, parf,
-        pard, scratch, red, sw, sp, total;
+        pard, scratch, red, sw, sp, solid, smask, inlet, total;
     int nslots;                   // diagnostics slots: step tiles, then island workgroups
     int ngroups;                  // groups of FP64-island mask words
     int nbx, nby, zc, nblocks, grid;  // step kernel: 64 x TH tiles of one plane,
@@ -88,6 +88,11 @@ Layout make_layout(const lbfd_grid& gr) {
     L.red = take(64 * sizeof(double));
     L.sw = take(sizeof(SurWeights));  // chemistry surrogate: packed weights
     L.sp = take(sizeof(SurPar));
+    // sharp-interface mode: per-cell solid flags and link masks; the inlet
+    // profile's equilibria per inlet row
+    L.solid = take(N);
+    L.smask = take(N * sizeof(uint32_t));
+    L.inlet = take((size_t)gr.ny * gr.nz * 19 * sizeof(double));
     L.total = off;
     return L;
 }
@@ -207,6 +212,13 @@ struct lbfd_ctx {
     // chemistry surrogate
     bool sur = false;
     int n_cu = 0;
+    // sharp-interface mode: solid flags of the phase field (phi >= 1/2, FP64
+    // decision), uploaded with it; the link masks are rebuilt on the device
+    // before the next step or read after the flags changed
+    std::vector<uint8_t> solid;
+    bool mask_dirty = true;
+    // velocity inlet profile [dim][ny*nz] (empty: the uniform u_in)
+    std::vector<double> prof;
 };
 
 namespace {
@@ -572,6 +584,28 @@ lbfd_status upload_tables(lbfd_ctx* c) {
                                      hipMemcpyHostToDevice, c->stream),
                    "upload parameters");
     if (st) return st;
+    if (!c->prof.empty()) {  // per-row inlet equilibria rho_in c_s^2 e_j(u(y, z))
+        const size_t nr = (size_t)c->grid.ny * c->grid.nz;
+        std::vector<double> eq(nr * 19, 0.0);
+        const int* cx = c->dim == 2 ? Lat<2>::cx : Lat<3>::cx;
+        const int* cy = c->dim == 2 ? Lat<2>::cy : Lat<3>::cy;
+        const int* cz = c->dim == 2 ? Lat<2>::cz : Lat<3>::cz;
+        for (size_t r = 0; r < nr; ++r) {
+            const double u0 = c->prof[r], u1 = c->prof[nr + r],
+                         u2 = c->dim > 2 ? c->prof[2 * nr + r] : 0.0;
+            const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+            for (int j = 0; j < c->Q; ++j) {
+                const double cu = cx[j] * u0 + cy[j] * u1 + cz[j] * u2;
+                eq[r * 19 + j] = c->params.rho_in * (1.0 / 3.0) * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+            }
+        }
+        st = hip_check(c, hipMemcpyAsync(dptr<char>(c, c->L.inlet), eq.data(), eq.size() * 8,
+                                         hipMemcpyHostToDevice, c->stream),
+                       "upload inlet profile");
+        if (st) return st;
+        st = hip_check(c, hipStreamSynchronize(c->stream), "upload inlet profile");
+        if (st) return st;
+    }
     // a closed domain keeps its P0 across new parameters
     if (c->params.closed && c->have_state && (st = launch_p0(c, 2))) return st;
     return hip_check(c, hipStreamSynchronize(c->stream), "upload parameters");
@@ -680,8 +714,28 @@ hipError_t time_mark(lbfd_ctx* c, int kernel, bool end) {
     return hipEventRecord(v[2 * slot + (end ? 1 : 0)], c->stream);
 }
 
+// Sharp-interface mode: link masks from the solid flags, when they changed
+lbfd_status ensure_si_mask(lbfd_ctx* c) {
+    if (!c->params.sharp_interface || !c->mask_dirty) return LBFD_OK;
+    hipError_t e;
+    if (c->fp32)
+        e = launch_si_mask_f32(c->dim, dptr<uint8_t>(c, c->L.solid),
+                               dptr<Par<float>>(c, c->L.parf), dptr<uint32_t>(c, c->L.smask),
+                               (int)c->N, c->stream);
+    else
+        e = launch_si_mask_f64(c->dim, dptr<uint8_t>(c, c->L.solid),
+                               dptr<Par<double>>(c, c->L.pard), dptr<uint32_t>(c, c->L.smask),
+                               (int)c->N, c->stream);
+    lbfd_status st = hip_check(c, e, "link mask kernel launch");
+    if (st) return st;
+    c->mask_dirty = false;
+    return LBFD_OK;
+}
+
 template <typename R>
 lbfd_status launch_step(lbfd_ctx* c, int phase) {
+    lbfd_status st = ensure_si_mask(c);
+    if (st) return st;
     StepArgs<R> a;
     const size_t N = c->N;
     a.g = dptr<R>(c, c->L.g);
@@ -691,6 +745,8 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.Y_nxt = dptr<R>(c, c->cur ? c->L.Y0 : c->L.Y1);
     a.divu = dptr<R>(c, c->L.divu);
     a.phi = dptr<R>(c, c->L.phi);
+    a.smask = c->params.sharp_interface ? dptr<uint32_t>(c, c->L.smask) : nullptr;
+    a.inlet_prof = c->prof.empty() ? nullptr : dptr<double>(c, c->L.inlet);
     a.partials = dptr<double>(c, c->L.part);
     a.flags = dptr<unsigned long long>(c, c->L.flags);
     a.P = dptr<Par<R>>(c, sizeof(R) == 4 ? c->L.parf : c->L.pard);
@@ -745,6 +801,8 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
 
 template <typename R>
 lbfd_status launch_macro(lbfd_ctx* c) {
+    lbfd_status st = ensure_si_mask(c);
+    if (st) return st;
     MacroArgs<R> a;
     const size_t N = c->N;
     a.g = dptr<R>(c, c->L.g);
@@ -752,6 +810,7 @@ lbfd_status launch_macro(lbfd_ctx* c) {
     a.Y = dptr<R>(c, c->cur ? c->L.Y1 : c->L.Y0);
     a.divu = dptr<R>(c, c->L.divu);
     a.phi = dptr<R>(c, c->L.phi);
+    a.smask = c->params.sharp_interface ? dptr<uint32_t>(c, c->L.smask) : nullptr;
     a.out = dptr<double>(c, c->L.scratch);
     a.P = dptr<Par<R>>(c, sizeof(R) == 4 ? c->L.parf : c->L.pard);
     a.PD = dptr<Par<double>>(c, c->L.pard);
@@ -868,6 +927,16 @@ lbfd_status lbfd_set_phase_field(lbfd_ctx* c, const double* phi) {
     if (st) return st;
     st = upload_field(c, c->L.phi, phi, c->N);
     if (st) return st;
+    // solid flags for the sharp-interface mode (the threshold taken in FP64)
+    c->solid.resize(c->N);
+    for (size_t i = 0; i < c->N; ++i) c->solid[i] = phi[i] >= 0.5 ? 1 : 0;
+    st = hip_check(c, hipMemcpyAsync(dptr<char>(c, c->L.solid), c->solid.data(), c->N,
+                                     hipMemcpyHostToDevice, c->stream),
+                   "upload solid flags");
+    if (st) return st;
+    st = hip_check(c, hipStreamSynchronize(c->stream), "upload solid flags");
+    if (st) return st;
+    c->mask_dirty = true;
     c->have_phi = true;
     return LBFD_OK;
 }
@@ -934,6 +1003,13 @@ lbfd_status lbfd_set_params(lbfd_ctx* c, const lbfd_params* p) {
         return fail(c, LBFD_E_STATE, "closing or opening the domain needs a new init_state");
     if (!(p->T_max >= 0.0) || !std::isfinite(p->T_max))
         return fail(c, LBFD_E_INVAL, "T_max must be finite and >= 0");
+    if (p->sharp_interface != 0 && p->sharp_interface != 1)
+        return fail(c, LBFD_E_INVAL, "sharp_interface must be 0 or 1");
+    if (p->sharp_interface && c->nsm > 4)
+        return fail(c, LBFD_E_UNSUPPORTED, "sharp-interface mode: at most 4 species");
+    if (p->sharp_interface && c->sur)
+        return fail(c, LBFD_E_UNSUPPORTED,
+                    "sharp-interface mode runs the exact reaction step (surrogate set)");
     lbfd_status st = check_stable(c, *p, c->have_mech ? &c->mech : nullptr);
     if (st) return st;
     st = set_device(c);
@@ -942,6 +1018,7 @@ lbfd_status lbfd_set_params(lbfd_ctx* c, const lbfd_params* p) {
     bool had = c->have_params;
     c->params = *p;
     c->have_params = true;
+    if (p->sharp_interface != old.sharp_interface) c->mask_dirty = true;
     st = upload_tables(c);
     if (st) {
         c->params = old;
@@ -1073,6 +1150,36 @@ lbfd_status lbfd_set_p0_state(lbfd_ctx* c, const double* in) {
     return hip_check(c, hipStreamSynchronize(c->stream), "closed-domain state");
 }
 
+lbfd_status lbfd_set_inlet_profile(lbfd_ctx* c, const double* u) {
+    if (!c) return LBFD_E_INVAL;
+    if (!u) {
+        c->prof.clear();
+        return LBFD_OK;
+    }
+    if (c->grid.lb_bc[0] != LBFD_LB_VELOCITY_INLET)
+        return fail(c, LBFD_E_INVAL, "inlet profile without a velocity inlet on the -x face");
+    const size_t nr = (size_t)c->grid.ny * c->grid.nz;
+    std::vector<double> prof(3 * nr, 0.0);
+    for (size_t r = 0; r < nr; ++r) {
+        double uu = 0.0;
+        for (int a = 0; a < c->dim; ++a) {
+            const double v = u[a * nr + r];
+            if (!std::isfinite(v)) return fail(c, LBFD_E_INVAL, "non-finite inlet velocity");
+            prof[a * nr + r] = v;
+            uu += v * v;
+        }
+        if (!(std::sqrt(uu) <= 0.1))
+            return fail(c, LBFD_E_INVAL, "inlet profile |u| > 0.1 (low-Mach limit)");
+    }
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    std::vector<double> old;
+    old.swap(c->prof);
+    c->prof = prof;
+    if ((st = upload_tables(c))) c->prof.swap(old);
+    return st;
+}
+
 lbfd_status lbfd_set_populations(lbfd_ctx* c, const double* g, const double* divu) {
     if (!c || !g) return LBFD_E_INVAL;
     if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
@@ -1148,7 +1255,12 @@ lbfd_status lbfd_read(lbfd_ctx* c, int32_t field, int32_t comp, double* out) {
                             inside = false;
                     }
                     const size_t id = ((size_t)z * n[1] + y) * n[0] + x;
-                    out[id] = inside ? nb[((size_t)p[2] * n[1] + p[1]) * n[0] + p[0]] : own[id];
+                    const size_t src = ((size_t)p[2] * n[1] + p[1]) * n[0] + p[0];
+                    // sharp-interface mode: a solid cell keeps its own slots,
+                    // a solid source is a wall
+                    if (c->params.sharp_interface && inside)
+                        inside = !c->solid[id] && !c->solid[src];
+                    out[id] = inside ? nb[src] : own[id];
                 }
         return LBFD_OK;
     }
@@ -1255,6 +1367,9 @@ lbfd_status lbfd_set_surrogate(lbfd_ctx* c, const float* w, const float* norm, c
     }
     if (!norm || !env) return LBFD_E_INVAL;
     if (!c->fp32) return fail(c, LBFD_E_UNSUPPORTED, "the surrogate runs in FP32 mode only");
+    if (c->have_params && c->params.sharp_interface)
+        return fail(c, LBFD_E_UNSUPPORTED,
+                    "sharp-interface mode runs the exact reaction step (no surrogate)");
     const int ns = c->ns, ni = 2 + ns, no = ns, H = MLP_H;
     if (ns < 1 || ni > MLP_KIN || no > MLP_OUT)
         return fail(c, LBFD_E_UNSUPPORTED, "surrogate needs 1..14 species");
@@ -1439,6 +1554,9 @@ lbfd_status halo_entry(lbfd_ctx* c, int32_t face, const void* buf, int pack) {
     if (face != -1 && face != 1) return fail(c, LBFD_E_INVAL, "halo face must be -1 or +1");
     if (c->grid.nx < 3) return fail(c, LBFD_E_INVAL, "a slab needs nx >= 3 (two halo planes)");
     if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
+    if (c->params.sharp_interface)
+        return fail(c, LBFD_E_UNSUPPORTED,
+                    "sharp-interface mode: the link masks do not cross slab faces");
     lbfd_status st = set_device(c);
     if (st) return st;
     void* b = const_cast<void*>(buf);

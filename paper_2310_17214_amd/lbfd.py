@@ -26,7 +26,7 @@ LB_BC = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
 FD_BC = {"periodic": 0, "dirichlet": 1, "neumann": 2}
 
 EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd_set_mechanism",
-            "lbfd_set_params", "lbfd_init_state", "lbfd_set_populations",
+            "lbfd_set_params", "lbfd_init_state", "lbfd_set_populations", "lbfd_set_inlet_profile",
             "lbfd_get_p0_state", "lbfd_set_p0_state", "lbfd_step",
             "lbfd_step_phase", "lbfd_read", "lbfd_diagnostics", "lbfd_synchronize",
             "lbfd_step_bytes_per_cell", "lbfd_set_timing", "lbfd_kernel_time",
@@ -60,7 +60,8 @@ class Params(C.Structure):
                 ("Le", C.c_double * MAX_SPECIES),
                 ("fd_face", (C.c_double * (1 + MAX_SPECIES)) * 6),
                 ("n_sub", C.c_int32), ("ign_threshold", C.c_double),
-                ("closed", C.c_int32), ("r_gas", C.c_double), ("T_max", C.c_double)]
+                ("closed", C.c_int32), ("r_gas", C.c_double), ("T_max", C.c_double),
+                ("sharp_interface", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -108,6 +109,7 @@ def lib():
         L.lbfd_set_params.argtypes = [vp, C.POINTER(Params)]
         L.lbfd_init_state.argtypes = [vp, _dp, _dp, _dp]
         L.lbfd_set_populations.argtypes = [vp, _dp, _dp]
+        L.lbfd_set_inlet_profile.argtypes = [vp, _dp]
         L.lbfd_get_p0_state.argtypes = [vp, _dp]
         L.lbfd_set_p0_state.argtypes = [vp, _dp]
         L.lbfd_step.argtypes = [vp, C.c_int32]
@@ -183,6 +185,7 @@ def make_params(s: dict) -> Params:
     p.n_sub, p.ign_threshold = s["n_sub"], s["theta_ign"]
     p.closed, p.r_gas = int(s.get("closed", 0)), float(s.get("r_gas", 0.0))
     p.T_max = float(s.get("T_max", 0.0))
+    p.sharp_interface = int(s.get("si", 0))
     return p
 
 
@@ -316,6 +319,14 @@ class Context:
         d = _f64(divu) if divu is not None else None
         self._check(lib().lbfd_set_populations(self._h, g.ctypes.data_as(_dp),
                                                None if d is None else d.ctypes.data_as(_dp)))
+
+    def set_inlet_profile(self, u):
+        """Velocity of each inlet row, u[a][z][y] for a < dim (None: uniform u_in)."""
+        if u is None:
+            self._check(lib().lbfd_set_inlet_profile(self._h, None))
+            return
+        u = _f64(u)
+        self._check(lib().lbfd_set_inlet_profile(self._h, u.ctypes.data_as(_dp)))
 
     def p0_state(self):
         """Closed domain: (S0, p, p_prev) for a checkpoint."""

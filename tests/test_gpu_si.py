@@ -1,0 +1,238 @@
+"""Sharp-interface reference mode and the velocity inlet profile on the GPU
+(HIP, gfx950) against the FP64 oracle, through the C ABI.
+
+Same error norm and bars as the diffuse-interface parity tests: FP64 mode
+<= 1e-12 (populations after one to three steps <= 1e-14); FP32 mode after
+1000 steps <= 1e-5 in u and <= 1e-4 in T and Y_k."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2310_17214_amd import calibration as CAL
+from paper_2310_17214_amd import workloads as W
+from setups import small_box
+
+pytestmark = pytest.mark.gpu
+
+
+def lb():
+    from paper_2310_17214_amd import lbfd
+
+    return lbfd
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def compare(ctx, orc):
+    g, r = ctx.fields(), orc.fields()
+    errs = {}
+    for k in ("T", "u", "Y", "Ph", "rho", "divu"):
+        if k not in r:
+            continue
+        if k in ("u", "Y"):
+            for c in range(r[k].shape[0]):
+                errs[f"{k}{c}"] = rel(g[k][c], r[k][c])
+        else:
+            errs[k] = rel(g[k], r[k])
+    return errs
+
+
+def _si_box():
+    """The all-boundary-kinds box in SI mode, about half of its cells solid,
+    with a sheared inlet profile."""
+    s, phi, T0, Y0, u0 = small_box()
+    s = dict(s, si=1)
+    ny, nz = s["ny"], s["nz"]
+    prof = np.zeros((3, nz, ny))
+    yy = (np.arange(ny) + 0.5) / ny
+    prof[0] = 0.02 + 0.01 * yy[None, :]
+    prof[1] = 0.002 * np.sin(np.arange(nz))[:, None]
+    return s, phi, T0, Y0, u0, prof
+
+
+def _both(s, phi, T0, Y0, u0, prof, steps):
+    ctx = lb().Context(s, phi)
+    orc = O.Oracle(s, phi)
+    if prof is not None:
+        ctx.set_inlet_profile(prof)
+        orc.set_inlet_profile(prof)
+    ctx.init_state(T0, Y0, u0)
+    orc.init_state(T0, Y0, u0)
+    ctx.step(steps)
+    orc.step(steps)
+    return ctx, orc
+
+
+def test_si_box_populations_after_odd_and_even_steps():
+    s, phi, T0, Y0, u0, prof = _si_box()
+    assert 0.2 < np.mean(phi >= 0.5) < 0.8
+    for n in (1, 2, 3):
+        say(f"si box fp64 steps={n}")
+        ctx, orc = _both(s, phi, T0, Y0, u0, prof, n)
+        gp, rp = ctx.populations(), orc.populations()
+        for i in range(19):
+            assert rel(gp[i], rp[i]) <= 1e-14, (n, i)
+        errs = compare(ctx, orc)
+        assert max(errs.values()) <= 1e-13, errs
+
+
+def test_si_box_fp64_60_steps_fields_and_diagnostics():
+    s, phi, T0, Y0, u0, prof = _si_box()
+    say("si box fp64 60 steps")
+    ctx, orc = _both(s, phi, T0, Y0, u0, prof, 60)
+    errs = compare(ctx, orc)
+    say(errs)
+    assert max(errs.values()) <= 1e-12, errs
+    f = ctx.fields()
+    solid = phi >= 0.5
+    # solid cells: at rest, state unchanged
+    assert np.abs(f["u"][:, solid]).max() == 0.0
+    assert np.abs(f["T"][solid] - T0[solid]).max() <= 1e-12 * T0.max()
+    dg, do = ctx.diagnostics(), orc.diag()
+    assert abs(dg["mass"] - do[O.D_MASS]) <= 1e-12 * do[O.D_MASS]
+    assert abs(dg["kinetic"] - do[O.D_KINETIC]) <= 1e-10 * do[O.D_KINETIC]
+    assert dg["n_tau_bad"] == do[O.D_TAUBAD] and dg["n_flagged_fp64"] == do[O.D_FLAGGED]
+
+
+def _si_crop(precision):
+    wl = W.bed_one_step(nx=129, ny=17, nz=15, precision=precision, bed=(8, 121), x_split=60,
+                        steps=0)
+    wl.setup["si"] = 1
+    wl.setup["theta_ign"] = 0.01
+    return wl
+
+
+def test_si_bed_crop_fp64_300_steps():
+    """The one-step flame in a crop of the sphere bed with sharp particles:
+    D3Q19, four species, the FP64 reaction step."""
+    wl = _si_crop("fp64")
+    say("si bed crop fp64 300 steps")
+    ctx, orc = _both(wl.setup, wl.phi, wl.T0, wl.Y0, None, None, 300)
+    errs = compare(ctx, orc)
+    say(errs)
+    assert max(errs.values()) <= 1e-12, errs
+
+
+def test_si_bed_crop_fp32_1000_steps():
+    """The same crop in FP32 (temperature offsets, 36 g populations, FP64
+    island for the flagged cells) against the FP64 oracle after 1000 steps."""
+    wl32, wl64 = _si_crop("fp32"), _si_crop("fp64")
+    say("si bed crop fp32 vs oracle, 1000 steps")
+    ctx = lb().Context(wl32.setup, wl32.phi)
+    ctx.init_state(wl32.T0, wl32.Y0)
+    ctx.step(1000)
+    orc = O.Oracle(wl64.setup, wl64.phi)
+    orc.init_state(wl64.T0, wl64.Y0)
+    orc.step(1000)
+    errs = compare(ctx, orc)
+    say(errs)
+    for k, e in errs.items():
+        if k.startswith("u"):
+            assert e <= 1e-5, (k, e)
+        if k == "T" or k.startswith("Y"):
+            assert e <= 1e-4, (k, e)
+    assert ctx.diagnostics()["n_flagged_fp64"] > 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_si_thermal_channel_d2q9(precision):
+    """The calibration channel (Sec. 4.2 setting, reduced: L = 20, eta = 4,
+    H = 3 L) in SI mode, D2Q9, parabolic inflow, hot walls: 2000 steps."""
+    s, phi, T0, prof, _ = CAL.channel(L=20, eta=4.0, H_over_L=3, thermal=True, si=True,
+                                      precision=precision)
+    s64 = dict(s, precision="fp64")
+    say(f"si thermal channel {precision} 2000 steps")
+    ctx = lb().Context(s, phi)
+    ctx.set_inlet_profile(prof)
+    ctx.init_state(T0)
+    ctx.step(2000)
+    orc = O.Oracle(s64, phi)
+    orc.set_inlet_profile(prof)
+    orc.init_state(T0)
+    orc.step(2000)
+    errs = compare(ctx, orc)
+    say(errs)
+    if precision == "fp64":
+        assert max(errs.values()) <= 1e-12, errs
+    else:
+        assert errs["u0"] <= 1e-5 and errs["u1"] <= 1e-5 and errs["T"] <= 1e-4, errs
+
+
+def test_si_without_solid_equals_di_without_coupling():
+    """SI mode with every phase-field value below 1/2 is the DI model with
+    the coupling off: bitwise the DI run with phi = 0."""
+    s, phi, T0, Y0, u0 = small_box()
+    phi_f = 0.49 * phi / phi.max()
+    a = lb().Context(dict(s, si=1), phi_f)
+    b = lb().Context(s, np.zeros_like(phi))
+    for c in (a, b):
+        c.init_state(T0, Y0, u0)
+        c.step(7)
+    fa, fb = a.fields(), b.fields()
+    for k in ("T", "u", "Y", "Ph", "divu"):
+        assert np.array_equal(fa[k], fb[k]), k
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_all_solid_box_is_frozen():
+    s, phi, T0, Y0, u0 = small_box()
+    ctx = lb().Context(dict(s, si=1), np.ones_like(phi))
+    ctx.init_state(T0, Y0, u0)
+    g0 = ctx.populations()
+    ctx.step(5)
+    f = ctx.fields()
+    assert np.array_equal(ctx.populations(), g0)
+    assert np.abs(f["T"] - T0).max() <= 1e-12 * T0.max()
+    assert np.abs(f["Y"] - Y0).max() == 0.0
+    assert np.abs(f["u"]).max() == 0.0
+
+
+def test_uniform_profile_equals_uniform_inlet():
+    s, phi, T0, Y0, u0 = small_box()
+    prof = np.zeros((3, s["nz"], s["ny"]))
+    prof[0] = s["u_in"][0]
+    a = lb().Context(s, phi)
+    b = lb().Context(s, phi)
+    b.set_inlet_profile(prof)
+    for c in (a, b):
+        c.init_state(T0, Y0, u0)
+        c.step(9)
+    assert np.array_equal(a.populations(), b.populations())
+    b.set_inlet_profile(None)
+    a.step(4)
+    b.step(4)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+def test_si_and_profile_arguments_are_checked():
+    s, phi, T0, Y0, u0 = small_box()
+    ctx = lb().Context(s, phi)
+    bad = np.zeros((3, s["nz"], s["ny"]))
+    bad[0, 0, 0] = 0.2  # above the low-Mach limit
+    with pytest.raises(Exception):
+        ctx.set_inlet_profile(bad)
+    bad[0, 0, 0] = float("nan")
+    with pytest.raises(Exception):
+        ctx.set_inlet_profile(bad)
+    closed = dict(s, lb_bc=["wall", "outlet"] + s["lb_bc"][2:])
+    c2 = lb().Context(closed, phi)
+    with pytest.raises(Exception):
+        c2.set_inlet_profile(np.zeros((3, s["nz"], s["ny"])))
+    # nine species: no sharp-interface kernels
+    s9 = W.periodic_box(3, 8, ns=9)
+    with pytest.raises(Exception):
+        lb().Context(dict(s9, si=1), np.zeros((8, 8, 8)))
+    # no halo exchange in SI mode
+    import torch
+
+    c3 = lb().Context(dict(s, si=1), phi)
+    c3.init_state(T0, Y0, u0)
+    buf = torch.zeros(c3.halo_bytes() // 8 + 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(Exception):
+        c3.halo_pack(1, buf)
