@@ -60,6 +60,8 @@ struct orc_ctx {
     double *phi, *g, *gs, *T, *Y, *divu;
     double *u, *Ph, *rho_n, *Tst, *Yst, *qT;
     double* uprof;                  /* inlet velocity per row [3][ny*nz], or NULL */
+    double* wout;                   /* characteristic outlet: incoming wave amplitude
+                                       per row [ny*nz]                            */
     double diag[ORC_D_LEN];
     double p_prev, S0;               /* closed domain: previous P0 / P0_in, and the
                                         sum of M / T of the initial state        */
@@ -365,8 +367,17 @@ static void lb_collide_phase(orc_ctx* o) {
  *   wall:            halfway bounce-back, gbar_i(x) = gbar*_opp(i)(x)
  *   velocity inlet:  g_i^eq(rho_in, u_in, P_h(x))
  *   pressure outlet: g_i^eq(rho(x), u(x), P_h = 0)
+ *   characteristic outlet: g_i^eq(rho(x), u(x), P_out) with
+ *                    P_out = w + rho(x) c_s u_x(x)
  * The paper uses no-slip walls, a prescribed inlet and an open
- * (non-reflecting) outlet; these are their simplest lattice forms.           */
+ * (non-reflecting) outlet.  The characteristic outlet follows the
+ * one-dimensional characteristic analysis of Poinsot and Lele that the paper
+ * cites: the amplitude of the wave entering through the outlet,
+ * w = P - rho c_s u_x, is held (an outgoing wave, which carries
+ * dP = rho c_s du_x, then leaves without reflection) and only relaxed
+ * towards the far-field pressure P_h = 0,
+ *   w^{n+1} = w^n - K P_h(x)^n,  K = sigma c_s (1 - Ma^2) / n_x,
+ * with Ma = |u_in| / c_s and n_x the domain length; w starts at 0.          */
 static void lb_stream_phase(orc_ctx* o) {
     const orc_setup* s = &o->s;
     int n[3] = {s->nx, s->ny, s->nz};
@@ -412,8 +423,10 @@ static void lb_stream_phase(orc_ctx* o) {
                             rho = s->rho_in;
                         } else {
                             for (int a = 0; a < 3; ++a) ub[a] = o->u[(long)a * o->N + id];
-                            ph = 0.0;
                             rho = o->rho_n[id];
+                            ph = 0.0;
+                            if (s->lb_bc[1] == ORC_LB_CHAR_OUTLET)
+                                ph = o->wout[(long)z * s->ny + y] + rho * sqrt(CS2) * ub[0];
                         }
                         eq_source(o->Q, o->c, o->w, rho, ub, ph, NULL, NULL, 0.0, geq, NULL);
                         val = geq[i];
@@ -423,6 +436,15 @@ static void lb_stream_phase(orc_ctx* o) {
                     o->g[(long)i * o->N + id] = val;
                 }
             }
+    if (s->lb_bc[1] == ORC_LB_CHAR_OUTLET) {
+        double uin2 = s->u_in[0] * s->u_in[0] + s->u_in[1] * s->u_in[1] + s->u_in[2] * s->u_in[2];
+        double K = s->outlet_sigma * sqrt(CS2) * (1.0 - uin2 / CS2) / s->nx;
+        for (int z = 0; z < s->nz; ++z)
+            for (int y = 0; y < s->ny; ++y) {
+                long id = cidx(o, s->nx - 1, y, z);
+                if (!is_solid(o, id)) o->wout[(long)z * s->ny + y] -= K * o->Ph[id];
+            }
+    }
 }
 
 /* ----------------------------------------------------------- FD phase */
@@ -689,6 +711,7 @@ orc_ctx* orc_create(const orc_setup* s, const double* phi_solid) {
     o->Tst = (double*)calloc(N, sizeof(double));
     o->Yst = (double*)calloc(ns * N, sizeof(double));
     o->qT = (double*)calloc(N, sizeof(double));
+    o->wout = (double*)calloc((size_t)s->ny * s->nz, sizeof(double));
     if (phi_solid) memcpy(o->phi, phi_solid, N * sizeof(double));
     return o;
 }
@@ -698,6 +721,7 @@ void orc_destroy(orc_ctx* o) {
     free(o->phi); free(o->g); free(o->gs); free(o->T); free(o->Y); free(o->divu);
     free(o->u); free(o->Ph); free(o->rho_n); free(o->Tst); free(o->Yst); free(o->qT);
     free(o->uprof);
+    free(o->wout);
     free(o);
 }
 
@@ -707,6 +731,7 @@ void orc_destroy(orc_ctx* o) {
 int orc_init_state(orc_ctx* o, const double* T, const double* Y, const double* u) {
     const orc_setup* s = &o->s;
     o->s.p0 = 1.0; /* a closed domain starts at P0 = P0_in */
+    memset(o->wout, 0, (size_t)s->ny * s->nz * sizeof(double));
     o->p_prev = 1.0;
     for (long id = 0; id < o->N; ++id) {
         double Yc[ORC_MAXS], uc[3] = {0.0, 0.0, 0.0}, geq[19];
@@ -799,6 +824,9 @@ int orc_read(const orc_ctx* o, int32_t field, int32_t comp, double* out) {
         return 0;
     case ORC_F_DIVU:
         memcpy(out, o->divu, o->N * sizeof(double));
+        return 0;
+    case ORC_F_OUTW:
+        memcpy(out, o->wout, (size_t)s->ny * s->nz * sizeof(double));
         return 0;
     case ORC_F_POP:
         if (comp < 0 || comp >= o->Q) return -1;

@@ -23,14 +23,15 @@
 #define ORC_MAXR 32 /* reactions */
 
 /* LB boundary kinds per face (-x,+x,-y,+y,-z,+z) */
-enum { ORC_LB_PERIODIC = 0, ORC_LB_WALL = 1, ORC_LB_INLET = 2, ORC_LB_OUTLET = 3 };
+enum { ORC_LB_PERIODIC = 0, ORC_LB_WALL = 1, ORC_LB_INLET = 2, ORC_LB_OUTLET = 3,
+       ORC_LB_CHAR_OUTLET = 4 };
 /* FD boundary kinds per face */
 enum { ORC_FD_PERIODIC = 0, ORC_FD_DIRICHLET = 1, ORC_FD_NEUMANN = 2 };
 /* phase bits for orc_step */
 enum { ORC_PH_LB = 1, ORC_PH_FD = 2, ORC_PH_CHEM = 4, ORC_PH_ALL = 7 };
 /* readable fields */
 enum { ORC_F_RHO = 0, ORC_F_U = 1, ORC_F_T = 2, ORC_F_Y = 3, ORC_F_PH = 4,
-       ORC_F_POP = 5, ORC_F_DIVU = 6 };
+       ORC_F_POP = 5, ORC_F_DIVU = 6, ORC_F_OUTW = 7 /* ny*nz values */ };
 /* diagnostics vector layout (doubles) */
 enum { ORC_D_MASS = 0, ORC_D_SPECIES = 1, ORC_D_ENTHALPY = 17, ORC_D_KINETIC = 18,
        ORC_D_UMAX = 19, ORC_D_TMIN = 20, ORC_D_TMAX = 21, ORC_D_NONFINITE = 22,
@@ -68,6 +69,10 @@ typedef struct {
      * heat conduction, no species or advective flux -- and the drag and
      * heat-exchange terms vanish.  0: the diffuse-interface model */
     int32_t si;
+    /* characteristic (non-reflecting) outlet, ORC_LB_CHAR_OUTLET on +x: the
+     * relaxation factor sigma of the incoming wave amplitude, Sec. 4 open
+     * boundary after Poinsot and Lele (> 0) */
+    double  outlet_sigma;
 } orc_setup;
 
 typedef struct orc_ctx orc_ctx;

@@ -18,10 +18,10 @@ LIB_PATH = os.path.join(HERE, "liblbfd_oracle.so")
 SRC = os.path.join(HERE, "lbfd_oracle.c")
 
 MAXS, MAXR = 16, 32
-LB = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
+LB = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3, "char_outlet": 4}
 FD = {"periodic": 0, "dirichlet": 1, "neumann": 2}
 PH_LB, PH_FD, PH_CHEM, PH_ALL = 1, 2, 4, 7
-F_RHO, F_U, F_T, F_Y, F_PH, F_POP, F_DIVU = range(7)
+F_RHO, F_U, F_T, F_Y, F_PH, F_POP, F_DIVU, F_OUTW = range(8)
 D_MASS, D_SPECIES, D_ENTHALPY, D_KINETIC, D_UMAX, D_TMIN, D_TMAX = 0, 1, 17, 18, 19, 20, 21
 D_NONFINITE, D_TAUBAD, D_NEGY, D_FLAGGED, D_FALLBACK, D_STEP, D_LEN = 22, 23, 24, 25, 26, 27, 28
 
@@ -44,7 +44,7 @@ class Setup(C.Structure):
         ("A", C.c_double * MAXR), ("beta", C.c_double * MAXR), ("theta", C.c_double * MAXR),
         ("rev", C.c_int32 * MAXR), ("lnKc_a", C.c_double * MAXR), ("lnKc_b", C.c_double * MAXR),
         ("closed", C.c_int32), ("r_gas", C.c_double), ("p0", C.c_double),
-        ("si", C.c_int32),
+        ("si", C.c_int32), ("outlet_sigma", C.c_double),
     ]
 
 
@@ -130,6 +130,7 @@ def make_setup(s: dict) -> Setup:
     st.r_gas = float(s.get("r_gas", 0.0))
     st.p0 = 1.0
     st.si = int(s.get("si", 0))
+    st.outlet_sigma = float(s.get("outlet_sigma", 0.0))
     return st
 
 
@@ -192,6 +193,12 @@ class Oracle:
         if self.ns:
             d["Y"] = np.stack([self.read(F_Y, k) for k in range(self.ns)])
         return d
+
+    def outlet_wave(self):
+        """Characteristic outlet: incoming wave amplitude per outlet row [nz][ny]."""
+        out = np.empty(self.N, np.float64)
+        lib().orc_read(self._h, F_OUTW, 0, _dp(out))
+        return out[: self.shape[0] * self.shape[1]].reshape(self.shape[:2]).copy()
 
     def populations(self):
         return np.stack([self.read(F_POP, i) for i in range(self.Q)])

@@ -23,7 +23,7 @@ from typing import Optional
 
 import numpy as np
 
-LB_BC = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
+LB_BC = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3, "char_outlet": 4}
 FD_BC = {"periodic": 0, "dirichlet": 1, "neumann": 2}
 MAX_SPECIES = 16
 MAX_REACTIONS = 32

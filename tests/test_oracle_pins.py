@@ -970,3 +970,66 @@ def test_inlet_profile_matches_uniform_inlet_and_shapes_the_flow():
     flux = ux.sum(0)
     assert np.abs(flux - flux[0]).max() < 1e-3 * flux[0]
     assert abs(flux[0] / prof[0, 0].sum() - 1.0) < 0.02
+
+
+# ------------------------------------------------- characteristic outlet
+
+def _pulse_run(kind, nx=300, steps=500, A=1e-4, width=8.0):
+    """A right-running acoustic pulse (P_h = A exp(-(x - x0)^2/(2 w^2)),
+    u_x = P_h/(rho c_s): the plane wave of the linearised equations, which
+    carries dP = rho c_s du) launched towards the +x face of a quiescent
+    D2Q9 strip.  Returns max |P_h| / A after `steps` steps."""
+    s = W.base_setup(2, nx, 1, 1, 0)
+    s["lb_bc"] = ["inlet", kind, "periodic", "periodic", "periodic", "periodic"]
+    s["fd_bc"] = ["dirichlet", "neumann", "periodic", "periodic", "periodic", "periodic"]
+    s["fd_val"][0] = [300.0]
+    s["mu_model"] = 0
+    s["outlet_sigma"] = 0.25
+    shape = (1, 1, nx)
+    o = O.Oracle(s, np.zeros(shape))
+    o.init_state(np.full(shape, 300.0))
+    x = np.arange(nx)
+    P = A * np.exp(-(x - nx / 2) ** 2 / (2 * width * width))
+    cs = math.sqrt(CS2)
+    g = np.zeros((9, nx))
+    for i in range(nx):
+        g[:, i], _ = O.eq_source(2, 1.0, [P[i] / cs, 0.0, 0.0], P[i], [0, 0, 0], [0, 0, 0], 0.0)
+    o.set_populations(g.reshape(9, 1, 1, nx))
+    o.step(steps)
+    return np.abs(o.read(O.F_PH)).max() / A
+
+
+def test_characteristic_outlet_lets_an_acoustic_pulse_leave():
+    """Sec. 4 open boundary (Poinsot-Lele characteristic treatment): a plane
+    acoustic pulse that reaches the outlet leaves the domain, while the
+    fixed-pressure equilibrium outlet reflects it (pressure node: the pulse
+    returns inverted at nearly full amplitude, less viscous damping)."""
+    assert _pulse_run("outlet") > 0.8
+    assert _pulse_run("char_outlet") < 0.02
+
+
+def test_characteristic_outlet_settles_to_the_uniform_inflow():
+    """Uniform inflow through a y-periodic strip: the characteristic outlet
+    relaxes the mean outlet pressure to P_h = 0, the incoming amplitude
+    w = P_h - rho c_s u_x then to -rho c_s u_in, and the uniform flow at
+    P_h = 0 is recovered everywhere."""
+    nx, ny, u_in = 60, 3, 0.03
+    s = W.base_setup(2, nx, ny, 1, 0)
+    s["lb_bc"] = ["inlet", "char_outlet", "periodic", "periodic", "periodic", "periodic"]
+    s["fd_bc"] = ["dirichlet", "neumann", "periodic", "periodic", "periodic", "periodic"]
+    s["fd_val"][0] = [300.0]
+    s["mu_model"] = 0
+    s["u_in"] = [u_in, 0.0, 0.0]
+    s["outlet_sigma"] = 0.25
+    shape = (1, ny, nx)
+    o = O.Oracle(s, np.zeros(shape))
+    u0 = np.zeros((2,) + shape)
+    u0[0] = u_in
+    o.init_state(np.full(shape, 300.0), None, u0)
+    o.step(8000)
+    f = o.fields()
+    assert np.abs(f["u"][0] - u_in).max() <= 1e-6 * u_in
+    assert np.abs(f["u"][1]).max() <= 1e-9
+    assert np.abs(f["Ph"]).max() <= 1e-7
+    w = o.outlet_wave()
+    assert np.abs(w + math.sqrt(CS2) * u_in).max() <= 1e-7
