@@ -72,7 +72,15 @@ typedef enum {
     LBFD_LB_PERIODIC = 0,
     LBFD_LB_WALL = 1,             /* halfway bounce-back (no slip)                 */
     LBFD_LB_VELOCITY_INLET = 2,   /* equilibrium at (rho_in, u_in, local P_h)      */
-    LBFD_LB_PRESSURE_OUTLET = 3   /* equilibrium at (local rho, local u, P_h = 0)  */
+    LBFD_LB_PRESSURE_OUTLET = 3,  /* equilibrium at (local rho, local u, P_h = 0)  */
+    LBFD_LB_CHARACTERISTIC_OUTLET = 4 /* non-reflecting open outlet (the Poinsot-Lele
+                                     characteristic treatment the paper uses, Sec. 4):
+                                     equilibrium at (local rho, local u, P_out) with
+                                     P_out = w + rho c_s u_x, where w, the amplitude
+                                     of the wave entering through the face, is kept
+                                     per outlet row and relaxed towards P_h = 0:
+                                     w <- w - K P_h, K = outlet_sigma c_s (1 - Ma^2)/nx,
+                                     Ma = |u_in|/c_s; w starts at 0 (init_state) */
 } lbfd_lb_bc;
 
 /* FD boundary kind per face; the +/- faces of an axis must both be periodic
@@ -128,6 +136,9 @@ typedef struct {
                                         Dirichlet face temperatures and, from
                                         lbfd_init_state on, the initial state's
                                         maximum.  0: no bound beyond those           */
+    double outlet_sigma;             /* characteristic outlet: relaxation factor of
+                                        the incoming wave (> 0; Poinsot and Lele
+                                        suggest about 0.25); unused otherwise       */
     int32_t sharp_interface;         /* 1: sharp-interface reference mode (Sec. 4: the
                                         coupling to the phase field switched off, the
                                         bulk phases separated at phi = 1/2).  Cells
@@ -182,7 +193,10 @@ typedef enum {
     LBFD_F_Y = 3,            /* component 0..ns-1                                 */
     LBFD_F_PH = 4,           /* hydrodynamic pressure of the current populations  */
     LBFD_F_POPULATIONS = 5,  /* component 0..Q-1, post-stream, natural layout     */
-    LBFD_F_DIVU = 6          /* thermal velocity divergence used by the next step */
+    LBFD_F_DIVU = 6,         /* thermal velocity divergence used by the next step */
+    LBFD_F_OUTLET_WAVE = 7   /* characteristic outlet: the incoming wave amplitude w
+                                per outlet row, ny*nz values (z*ny + y); part of a
+                                checkpoint (lbfd_set_outlet_wave restores it)    */
 } lbfd_field;
 
 /* phase bits of lbfd_step_phase (test hook; lbfd_step runs all three) */
@@ -304,6 +318,13 @@ lbfd_status lbfd_set_populations(lbfd_ctx* ctx, const double* g, const double* d
  * LBFD_E_INVAL when the -x face is no velocity inlet, for non-finite values
  * or for |u| > 0.1 (the low-Mach limit). */
 lbfd_status lbfd_set_inlet_profile(lbfd_ctx* ctx, const double* u);
+
+/* Characteristic outlet: overwrite the incoming wave amplitude w of every
+ * outlet row (ny*nz doubles, z*ny + y, host memory) -- with lbfd_init_state
+ * and lbfd_set_populations this restores a checkpoint.  LBFD_E_INVAL for
+ * non-finite values or a grid without that outlet; LBFD_E_STATE before
+ * lbfd_init_state. */
+lbfd_status lbfd_set_outlet_wave(lbfd_ctx* ctx, const double* w);
 
 /* Closed domain (Sec. 3.1): the thermodynamic-pressure state that a checkpoint
  * needs besides the fields: out/in[3] = {S0, p, p_prev}, the sum of M/T over

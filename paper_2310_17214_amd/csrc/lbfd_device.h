@@ -25,7 +25,7 @@ enum {
     DG_COUNT = 31
 };
 static_assert(DG_COUNT <= DIAG_STRIDE, "diagnostic slot layout");
-enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INLET = 2, BC_OUTLET = 3 };
+enum { BC_PERIODIC = 0, BC_WALL = 1, BC_INLET = 2, BC_OUTLET = 3, BC_CHAR_OUTLET = 4 };
 enum { FD_PERIODIC = 0, FD_DIRICHLET = 1, FD_NEUMANN = 2 };
 enum { PH_LB = 1, PH_FD = 2, PH_CHEM = 4 };
 
@@ -72,6 +72,9 @@ struct Par {
     R theta_ign, h_sub;
     R u_in[3], F_b[3];
     R inlet_eq[19];   // rho_in c_s^2 e_j(u_in): the inlet equilibria less their P_h part
+    int char_out;     // +x face is the characteristic (non-reflecting) outlet
+    R K_out;          // its relaxation factor sigma c_s (1 - Ma^2) / nx
+    R c_s;            // sqrt(1/3), rounded once on the host
     R fd_face[6][1 + MAXS];  // Dirichlet face values: T - T_ref, then Y_k
     R rD_fac[MAXS];   // 1/(cp Le_k)
     R M[MAXS], invM[MAXS], dhf[MAXS], mu_star[MAXS];
@@ -393,6 +396,8 @@ struct StepArgs {
     const uint32_t* smask;     // [N] sharp-interface link masks (SI kernels only)
     const double* inlet_prof;  // [ny*nz][19] rho_in c_s^2 e_j(u_in(y, z)) per inlet row,
                                // or null: the uniform inlet_eq of the parameters
+    double* outlet_w;          // [ny*nz] characteristic outlet: incoming wave amplitude
+                               // per outlet row (read and rewritten by the row's cell)
     double* partials;     // [nblocks][DIAG_STRIDE]
     unsigned long long* flags;  // [nblocks][zc][waves] reaction-active cells (FP32 mode)
     const Par<R>* P;

@@ -32,7 +32,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
     size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, gtot, list, count, p0, p0part, parf,
-        pard, scratch, red, sw, sp, solid, smask, inlet, total;
+        pard, scratch, red, sw, sp, solid, smask, inlet, outw, total;
     int nslots;                   // diagnostics slots: step tiles, then island workgroups
     int ngroups;                  // groups of FP64-island mask words
     int nbx, nby, zc, nblocks, grid;  // step kernel: 64 x TH tiles of one plane,
@@ -93,6 +93,7 @@ Layout make_layout(const lbfd_grid& gr) {
     L.solid = take(N);
     L.smask = take(N * sizeof(uint32_t));
     L.inlet = take((size_t)gr.ny * gr.nz * 19 * sizeof(double));
+    L.outw = take((size_t)gr.ny * gr.nz * sizeof(double));  // characteristic outlet
     L.total = off;
     return L;
 }
@@ -457,6 +458,13 @@ Par<R> build_par(const lbfd_ctx* c) {
             P.inlet_eq[j] = (R)(p.rho_in * (1.0 / 3.0) * e);
         }
     }
+    {  // characteristic outlet: K = sigma c_s (1 - Ma^2) / nx, Ma = |u_in| / c_s
+        const double cs = std::sqrt(1.0 / 3.0);
+        const double uin2 = p.u_in[0] * p.u_in[0] + p.u_in[1] * p.u_in[1] + p.u_in[2] * p.u_in[2];
+        P.char_out = g.lb_bc[1] == LBFD_LB_CHARACTERISTIC_OUTLET;
+        P.K_out = (R)(p.outlet_sigma * cs * (1.0 - uin2 / (1.0 / 3.0)) / g.nx);
+        P.c_s = (R)cs;
+    }
     double im_in = 0.0;
     int corr = 0;
     for (int k = 0; k < c->ns; ++k) {
@@ -678,14 +686,14 @@ lbfd_status validate_grid(const lbfd_grid* g, std::string& msg) {
     const int nf = g->dim == 2 ? 4 : 6;
     for (int f = 0; f < 6; ++f) {
         const int lb = g->lb_bc[f], fd = g->fd_bc[f];
-        if (lb < 0 || lb > 3 || fd < 0 || fd > 2) return msg = "unknown boundary kind", LBFD_E_INVAL;
+        if (lb < 0 || lb > 4 || fd < 0 || fd > 2) return msg = "unknown boundary kind", LBFD_E_INVAL;
         if (f >= nf && (lb != LBFD_LB_PERIODIC || fd != LBFD_FD_PERIODIC))
             return msg = "z faces of a 2-D grid must be periodic", LBFD_E_INVAL;
         if ((lb == LBFD_LB_PERIODIC) != (fd == LBFD_FD_PERIODIC))
             return msg = "LB and FD must agree on periodic faces", LBFD_E_INVAL;
         if (lb == LBFD_LB_VELOCITY_INLET && f != 0)
             return msg = "velocity inlet only on the -x face", LBFD_E_UNSUPPORTED;
-        if (lb == LBFD_LB_PRESSURE_OUTLET && f != 1)
+        if ((lb == LBFD_LB_PRESSURE_OUTLET || lb == LBFD_LB_CHARACTERISTIC_OUTLET) && f != 1)
             return msg = "pressure outlet only on the +x face", LBFD_E_UNSUPPORTED;
     }
     for (int a = 0; a < 3; ++a)
@@ -747,6 +755,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.phi = dptr<R>(c, c->L.phi);
     a.smask = c->params.sharp_interface ? dptr<uint32_t>(c, c->L.smask) : nullptr;
     a.inlet_prof = c->prof.empty() ? nullptr : dptr<double>(c, c->L.inlet);
+    a.outlet_w = dptr<double>(c, c->L.outw);
     a.partials = dptr<double>(c, c->L.part);
     a.flags = dptr<unsigned long long>(c, c->L.flags);
     a.P = dptr<Par<R>>(c, sizeof(R) == 4 ? c->L.parf : c->L.pard);
@@ -994,13 +1003,17 @@ lbfd_status lbfd_set_params(lbfd_ctx* c, const lbfd_params* p) {
     if (p->closed) {
         for (int f = 0; f < 6; ++f)
             if (c->grid.lb_bc[f] == LBFD_LB_VELOCITY_INLET ||
-                c->grid.lb_bc[f] == LBFD_LB_PRESSURE_OUTLET)
+                c->grid.lb_bc[f] == LBFD_LB_PRESSURE_OUTLET ||
+                c->grid.lb_bc[f] == LBFD_LB_CHARACTERISTIC_OUTLET)
                 return fail(c, LBFD_E_INVAL, "a closed domain has no inlet or outlet face");
         if (!(p->r_gas >= 0.0) || !(p->r_gas < p->cp))
             return fail(c, LBFD_E_INVAL, "closed domain: 0 <= r_gas < cp");
     }
     if (c->have_state && c->have_params && p->closed != c->params.closed)
         return fail(c, LBFD_E_STATE, "closing or opening the domain needs a new init_state");
+    if (c->grid.lb_bc[1] == LBFD_LB_CHARACTERISTIC_OUTLET &&
+        !(std::isfinite(p->outlet_sigma) && p->outlet_sigma > 0.0))
+        return fail(c, LBFD_E_INVAL, "characteristic outlet: outlet_sigma must be > 0");
     if (!(p->T_max >= 0.0) || !std::isfinite(p->T_max))
         return fail(c, LBFD_E_INVAL, "T_max must be finite and >= 0");
     if (p->sharp_interface != 0 && p->sharp_interface != 1)
@@ -1081,6 +1094,11 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
     st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.gtot), 0,
                                      (size_t)c->L.ngroups * GSPREAD * sizeof(int), c->stream),
                    "clear island group counts");
+    if (st) return st;
+    // characteristic outlet: the incoming wave amplitude starts at zero
+    st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.outw), 0,
+                                     (size_t)c->grid.ny * c->grid.nz * sizeof(double), c->stream),
+                   "clear outlet state");
     if (st) return st;
     st = hip_check(c, hipStreamSynchronize(c->stream), "init");
     if (st) return st;
@@ -1180,6 +1198,23 @@ lbfd_status lbfd_set_inlet_profile(lbfd_ctx* c, const double* u) {
     return st;
 }
 
+lbfd_status lbfd_set_outlet_wave(lbfd_ctx* c, const double* w) {
+    if (!c || !w) return LBFD_E_INVAL;
+    if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
+    if (c->grid.lb_bc[1] != LBFD_LB_CHARACTERISTIC_OUTLET)
+        return fail(c, LBFD_E_INVAL, "no characteristic outlet");
+    const size_t nr = (size_t)c->grid.ny * c->grid.nz;
+    for (size_t i = 0; i < nr; ++i)
+        if (!std::isfinite(w[i])) return fail(c, LBFD_E_INVAL, "non-finite outlet state");
+    lbfd_status st = set_device(c);
+    if (st) return st;
+    st = hip_check(c, hipMemcpyAsync(dptr<char>(c, c->L.outw), w, nr * 8, hipMemcpyHostToDevice,
+                                     c->stream),
+                   "set outlet state");
+    if (st) return st;
+    return hip_check(c, hipStreamSynchronize(c->stream), "set outlet state");
+}
+
 lbfd_status lbfd_set_populations(lbfd_ctx* c, const double* g, const double* divu) {
     if (!c || !g) return LBFD_E_INVAL;
     if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
@@ -1228,6 +1263,14 @@ lbfd_status lbfd_read(lbfd_ctx* c, int32_t field, int32_t comp, double* out) {
         return download_field(c, (c->cur ? c->L.Y1 : c->L.Y0) + comp * N * s, out, N);
     case LBFD_F_DIVU:
         return download_field(c, c->L.divu, out, N);
+    case LBFD_F_OUTLET_WAVE: {
+        const size_t nr = (size_t)c->grid.ny * c->grid.nz;
+        st = hip_check(c, hipMemcpyAsync(out, dptr<double>(c, c->L.outw), nr * 8,
+                                         hipMemcpyDeviceToHost, c->stream),
+                       "read outlet state");
+        if (st) return st;
+        return hip_check(c, hipStreamSynchronize(c->stream), "read outlet state");
+    }
     case LBFD_F_POPULATIONS: {
         if (comp < 0 || comp >= c->Q) return fail(c, LBFD_E_INVAL, "population index");
         // (the populations are stored scaled: 36 g in FP32 mode)

@@ -20,13 +20,14 @@ LBFD_E_STATE, LBFD_E_NUMERIC, LBFD_E_UNSUPPORTED = -4, -5, -6
 STATUS = {0: "OK", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_STATE",
           -5: "E_NUMERIC", -6: "E_UNSUPPORTED"}
 FP64, FP32 = 0, 1
-F_RHO, F_U, F_T, F_Y, F_PH, F_POPULATIONS, F_DIVU = range(7)
+F_RHO, F_U, F_T, F_Y, F_PH, F_POPULATIONS, F_DIVU, F_OUTLET_WAVE = range(8)
 PHASE_LB, PHASE_FD, PHASE_CHEM, PHASE_ALL = 1, 2, 4, 7
-LB_BC = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3}
+LB_BC = {"periodic": 0, "wall": 1, "inlet": 2, "outlet": 3, "char_outlet": 4}
 FD_BC = {"periodic": 0, "dirichlet": 1, "neumann": 2}
 
 EXPORTED = ["lbfd_workspace_bytes", "lbfd_create", "lbfd_set_phase_field", "lbfd_set_mechanism",
             "lbfd_set_params", "lbfd_init_state", "lbfd_set_populations", "lbfd_set_inlet_profile",
+            "lbfd_set_outlet_wave",
             "lbfd_get_p0_state", "lbfd_set_p0_state", "lbfd_step",
             "lbfd_step_phase", "lbfd_read", "lbfd_diagnostics", "lbfd_synchronize",
             "lbfd_step_bytes_per_cell", "lbfd_set_timing", "lbfd_kernel_time",
@@ -61,7 +62,7 @@ class Params(C.Structure):
                 ("fd_face", (C.c_double * (1 + MAX_SPECIES)) * 6),
                 ("n_sub", C.c_int32), ("ign_threshold", C.c_double),
                 ("closed", C.c_int32), ("r_gas", C.c_double), ("T_max", C.c_double),
-                ("sharp_interface", C.c_int32)]
+                ("outlet_sigma", C.c_double), ("sharp_interface", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -110,6 +111,7 @@ def lib():
         L.lbfd_init_state.argtypes = [vp, _dp, _dp, _dp]
         L.lbfd_set_populations.argtypes = [vp, _dp, _dp]
         L.lbfd_set_inlet_profile.argtypes = [vp, _dp]
+        L.lbfd_set_outlet_wave.argtypes = [vp, _dp]
         L.lbfd_get_p0_state.argtypes = [vp, _dp]
         L.lbfd_set_p0_state.argtypes = [vp, _dp]
         L.lbfd_step.argtypes = [vp, C.c_int32]
@@ -186,6 +188,7 @@ def make_params(s: dict) -> Params:
     p.closed, p.r_gas = int(s.get("closed", 0)), float(s.get("r_gas", 0.0))
     p.T_max = float(s.get("T_max", 0.0))
     p.sharp_interface = int(s.get("si", 0))
+    p.outlet_sigma = float(s.get("outlet_sigma", 0.0))
     return p
 
 
@@ -351,6 +354,16 @@ class Context:
         out = np.empty(self.N, np.float64)
         self._check(lib().lbfd_read(self._h, int(field), int(comp), out.ctypes.data_as(_dp)))
         return out.reshape(self.shape)
+
+    def outlet_wave(self):
+        """Characteristic outlet: incoming wave amplitude per outlet row [nz][ny]."""
+        out = np.empty(self.N, np.float64)
+        self._check(lib().lbfd_read(self._h, F_OUTLET_WAVE, 0, out.ctypes.data_as(_dp)))
+        return out[: self.shape[0] * self.shape[1]].reshape(self.shape[:2]).copy()
+
+    def set_outlet_wave(self, w):
+        w = _f64(w)
+        self._check(lib().lbfd_set_outlet_wave(self._h, w.ctypes.data_as(_dp)))
 
     def fields(self):
         d = {"rho": self.read(F_RHO), "T": self.read(F_T), "Ph": self.read(F_PH),
