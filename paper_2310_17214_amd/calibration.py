@@ -194,7 +194,8 @@ def run_channel(setup, phi, T0, prof, max_steps=200000, chunk=2000, tol=1e-7, se
     return ux, T, steps
 
 
-def sweep(kind, values, eta, shape="sine", L=50, A_u_fixed=None, log=None, **kw):
+def sweep(kind, values, eta, shape="sine", L=50, A_u_fixed=None, log=None, max_steps=200000,
+          **kw):
     """MSE of the DI section profile against the SI one for each coupling
     value.  kind 'A_u': isothermal channel, f = u_x (Sec. 4.1); kind 'A_T':
     thermal channel, f = T (Sec. 4.2), with A_u at A_u_fixed."""
@@ -203,22 +204,31 @@ def sweep(kind, values, eta, shape="sine", L=50, A_u_fixed=None, log=None, **kw)
     if thermal and A_u_fixed is not None:
         base["A_u"] = A_u_fixed
     s, phi, T0, prof, y = channel(si=True, **base)
-    u_si, T_si, n_si = run_channel(s, phi, T0, prof)
+    u_si, T_si, n_si = run_channel(s, phi, T0, prof, max_steps=max_steps)
     f_si = T_si if thermal else u_si
     fluid = (y > 0) & (y < L)
     out = {"kind": kind, "eta": eta, "shape": shape, "L": L, "si_steps": n_si, "runs": []}
+    from . import lbfd
+
     for v in values:
         args = dict(base)
         args["A_T" if thermal else "A_u"] = v
         s, phi, T0, prof, _ = channel(si=False, **args)
-        u_di, T_di, n = run_channel(s, phi, T0, prof)
+        try:
+            u_di, T_di, n = run_channel(s, phi, T0, prof, max_steps=max_steps)
+        except lbfd.LbfdError as e:  # e.g. beyond the explicit-stability rule
+            out["runs"].append({"value": float(v), "refused": str(e)})
+            if log:
+                log(f"  {kind} = {v:g}: refused ({e})")
+            continue
         f_di = T_di if thermal else u_di
         e = mse(f_si[fluid], f_di[fluid], y[fluid], L, eta)
         out["runs"].append({"value": float(v), "mse": e, "steps": n})
         if log:
             log(f"  {kind} = {v:g}: MSE {e:.4e} ({n} steps)")
-    vals = [r["value"] for r in out["runs"]]
-    errs = [r["mse"] for r in out["runs"]]
+    ok = [r for r in out["runs"] if "mse" in r]
+    vals = [r["value"] for r in ok]
+    errs = [r["mse"] for r in ok]
     best, bracketed = refine_minimum(vals, errs)
     out["optimum"] = best
     out["bracketed"] = bracketed
@@ -263,7 +273,8 @@ def main(argv=None):
     log(f"A_T sweep at A_u = {ru['optimum']:.1f}")
     rt = sweep("A_T", a.A_T, a.eta, a.shape, a.L, A_u_fixed=ru["optimum"], log=log)
     log(f"A_T* = {rt['optimum']:.1f} (bracketed: {rt['bracketed']})")
-    res = {"A_u": ru, "A_T": rt}
+    res = {"command": "python -m paper_2310_17214_amd.calibration " + " ".join(argv or sys.argv[1:]),
+           "A_u": ru, "A_T": rt}
     if a.poiseuille:
         err, n = si_poiseuille()
         log(f"SI Poiseuille (L = 40, H = 40 L, Re = 100): max deviation {err:.3e} "

@@ -236,3 +236,16 @@ def test_si_and_profile_arguments_are_checked():
     buf = torch.zeros(c3.halo_bytes() // 8 + 1, dtype=torch.float64, device="cuda")
     with pytest.raises(Exception):
         c3.halo_pack(1, buf)
+
+
+def test_calibration_sweep_brackets_a_minimum():
+    """The calibration loop end to end on a small channel (L = 20, eta = 4,
+    tanh profile, H = 2 L): the DI-vs-SI error of Eq. mean-standard-error-f
+    is larger at A_u = 20 and at 2000 than near the optimum, so the sweep
+    brackets a minimum (too weak a drag leaks flow into the interface, too
+    strong a drag moves the effective wall into the fluid)."""
+    r = CAL.sweep("A_u", [20.0, 150.0, 2000.0], 4.0, "tanh", 20, H_over_L=2, max_steps=60000)
+    say(r)
+    e = [x["mse"] for x in r["runs"]]
+    assert e[1] < e[0] and e[1] < e[2] and r["bracketed"]
+    assert 20.0 < r["optimum"] < 2000.0
