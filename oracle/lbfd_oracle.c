@@ -583,13 +583,160 @@ static void rates(const orc_setup* s, double T, const double* Y, double rho, dou
     *wT = w;
 }
 
+void orc_rates(const orc_setup* s, double T, const double* Y, double rho, double* wk,
+               double* wT) {
+    rates(s, T, Y, rho, wk, wT);
+}
+
+/* Right-hand side f of the reaction step and its Jacobian at fixed density:
+ * with [X_m] = rho Y_m / M_m and the law of mass action,
+ *   d Q_j / d[X_m] = k_f nu'_mj [X_m]^(nu'_mj - 1) prod_{l != m} [X_l]^nu'_lj
+ *                  - k_r nu''_mj [X_m]^(nu''_mj - 1) prod_{l != m} [X_l]^nu''_lj
+ *   d Q_j / dT     = Q_f,j dln k_f/dT - Q_r,j dln k_r/dT,
+ *     dln k_f/dT = beta/T + theta/T^2,  dln k_r/dT = dln k_f/dT + b/T^2
+ *     (k_r = k_f / exp(a + b/T)),
+ * and f_k = (M_k/rho) sum_j s_kj Q_j, f_T = -sum_k dh_f,k f_k / cp:
+ *   d f_k/d Y_m = (M_k/M_m) sum_j s_kj d Q_j/d[X_m],
+ *   d f_k/dT    = (M_k/rho) sum_j s_kj d Q_j/dT,
+ *   d f_T/d y   = -sum_k dh_f,k d f_k/d y / cp.                              */
+static double ipow(double x, int n) {
+    double r = 1.0;
+    for (int p = 0; p < n; ++p) r *= x;
+    return r;
+}
+void orc_rates_jacobian(const orc_setup* s, double T, const double* Y, double rho, double* f,
+                        double* J) {
+    int ns = s->ns, n = ns + 1;
+    double X[ORC_MAXS], G[ORC_MAXS][ORC_MAXS], GT[ORC_MAXS], w[ORC_MAXS];
+    for (int k = 0; k < ns; ++k) {
+        X[k] = rho * Y[k] / s->M[k];
+        w[k] = GT[k] = 0.0;
+        for (int m = 0; m < ns; ++m) G[k][m] = 0.0;
+    }
+    for (int j = 0; j < s->nr; ++j) {
+        double kf = s->A[j] * pow(T, s->beta[j]) * exp(-s->theta[j] / T);
+        double dlf = s->beta[j] / T + s->theta[j] / (T * T);
+        double kr = s->rev[j] ? kf / exp(s->lnKc_a[j] + s->lnKc_b[j] / T) : 0.0;
+        double dlr = dlf + s->lnKc_b[j] / (T * T);
+        double qf = kf, qr = kr, dQ[ORC_MAXS];
+        for (int k = 0; k < ns; ++k) {
+            qf *= ipow(X[k], s->nu_f[j][k]);
+            qr *= ipow(X[k], s->nu_r[j][k]);
+        }
+        for (int m = 0; m < ns; ++m) {
+            double df = 0.0, dr = 0.0;
+            if (s->nu_f[j][m] > 0) {
+                df = kf * s->nu_f[j][m] * ipow(X[m], s->nu_f[j][m] - 1);
+                for (int l = 0; l < ns; ++l)
+                    if (l != m) df *= ipow(X[l], s->nu_f[j][l]);
+            }
+            if (s->rev[j] && s->nu_r[j][m] > 0) {
+                dr = kr * s->nu_r[j][m] * ipow(X[m], s->nu_r[j][m] - 1);
+                for (int l = 0; l < ns; ++l)
+                    if (l != m) dr *= ipow(X[l], s->nu_r[j][l]);
+            }
+            dQ[m] = df - dr;
+        }
+        double Qj = qf - qr, dQT = qf * dlf - qr * dlr;
+        for (int k = 0; k < ns; ++k) {
+            double skj = (double)(s->nu_r[j][k] - s->nu_f[j][k]);
+            if (skj == 0.0) continue;
+            w[k] += skj * Qj;
+            GT[k] += skj * dQT;
+            for (int m = 0; m < ns; ++m) G[k][m] += skj * dQ[m];
+        }
+    }
+    double fT = 0.0;
+    for (int i = 0; i < n * n; ++i) J[i] = 0.0;
+    for (int k = 0; k < ns; ++k) {
+        f[k] = s->M[k] * w[k] / rho;
+        fT -= s->dhf[k] * f[k] / s->cp;
+        for (int m = 0; m < ns; ++m) J[k * n + m] = s->M[k] / s->M[m] * G[k][m];
+        J[k * n + ns] = s->M[k] / rho * GT[k];
+    }
+    f[ns] = fT;
+    for (int m = 0; m < n; ++m) {
+        double v = 0.0;
+        for (int k = 0; k < ns; ++k) v -= s->dhf[k] * J[k * n + m];
+        J[ns * n + m] = v / s->cp;
+    }
+}
+
+/* Solve A x = b in place (b becomes x) by Gaussian elimination with partial
+ * pivoting; A (n x n, row-major) is overwritten.  Returns -1 for a singular A. */
+static int lu_solve(int n, double* A, double* b) {
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(A[r * n + c]) > fabs(A[p * n + c])) p = r;
+        if (A[p * n + c] == 0.0) return -1;
+        if (p != c) {
+            for (int q = 0; q < n; ++q) {
+                double t = A[c * n + q];
+                A[c * n + q] = A[p * n + q];
+                A[p * n + q] = t;
+            }
+            double t = b[c];
+            b[c] = b[p];
+            b[p] = t;
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double l = A[r * n + c] / A[c * n + c];
+            for (int q = c; q < n; ++q) A[r * n + q] -= l * A[c * n + q];
+            b[r] -= l * b[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        double v = b[c];
+        for (int q = c + 1; q < n; ++q) v -= A[c * n + q] * b[q];
+        b[c] = v / A[c * n + c];
+    }
+    return 0;
+}
+
 /* Reaction sub-step after transport (Lie splitting; the paper's solver takes
- * its integrator from the kinetics library): n_sub explicit Euler sub-steps
- * of dY_k/dt = omega_k/rho, dT/dt = omega_T/(rho cp) at constant pressure,
- * rho re-evaluated from the EOS at each sub-step.                            */
+ * its integrator from the kinetics library) of dY_k/dt = omega_k/rho,
+ * dT/dt = omega_T/(rho cp) at constant pressure, over one time step:
+ *   scheme 0: n_sub explicit Euler sub-steps, rho re-evaluated from the EOS
+ *             at each;
+ *   scheme 1: n_sub linearly implicit Euler (one-stage Rosenbrock) sub-steps
+ *             of length h = 1/n_sub, (I - h J) dy = h f, y += dy, with f and
+ *             J at the sub-step's state and density;
+ *   scheme 2: n = min(n_sub, max(1, ceil(2 kappa))) explicit Euler sub-steps
+ *             of length 1/n, kappa = max_i |J_ii| at the cell's state (the
+ *             explicit step then keeps h kappa <= 1/2).                     */
 static void chem_integrate(const orc_setup* s, double* T, double* Y) {
-    double h = 1.0 / s->n_sub, wk[ORC_MAXS], wT;
-    for (int n = 0; n < s->n_sub; ++n) {
+    double wk[ORC_MAXS], wT;
+    int nsub = s->n_sub, ns = s->ns, n = ns + 1;
+    if (s->chem_scheme == 1) {
+        double h = 1.0 / nsub, f[ORC_MAXS + 1], J[(ORC_MAXS + 1) * (ORC_MAXS + 1)];
+        for (int it = 0; it < nsub; ++it) {
+            double rho = orc_eos(s, *T, Y);
+            orc_rates_jacobian(s, *T, Y, rho, f, J);
+            for (int i = 0; i < n * n; ++i) J[i] = -h * J[i];
+            for (int i = 0; i < n; ++i) {
+                J[i * n + i] += 1.0;
+                f[i] *= h;
+            }
+            if (lu_solve(n, J, f) != 0) {
+                *T = NAN;
+                return;
+            }
+            for (int k = 0; k < ns; ++k) Y[k] += f[k];
+            *T += f[ns];
+        }
+        return;
+    }
+    if (s->chem_scheme == 2) {
+        double f[ORC_MAXS + 1], J[(ORC_MAXS + 1) * (ORC_MAXS + 1)], kap = 0.0;
+        orc_rates_jacobian(s, *T, Y, orc_eos(s, *T, Y), f, J);
+        for (int i = 0; i < n; ++i)
+            if (fabs(J[i * n + i]) > kap) kap = fabs(J[i * n + i]);
+        double m = ceil(2.0 * kap);
+        nsub = m < 1.0 ? 1 : m > (double)s->n_sub ? s->n_sub : (int)m;
+    }
+    double h = 1.0 / nsub;
+    for (int it = 0; it < nsub; ++it) {
         double rho = orc_eos(s, *T, Y);
         rates(s, *T, Y, rho, wk, &wT);
         for (int k = 0; k < s->ns; ++k) Y[k] = Y[k] + h * wk[k] / rho;

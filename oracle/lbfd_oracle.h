@@ -73,6 +73,15 @@ typedef struct {
      * relaxation factor sigma of the incoming wave amplitude, Sec. 4 open
      * boundary after Poinsot and Lele (> 0) */
     double  outlet_sigma;
+    /* reaction step (Lie-split after transport; the paper takes its
+     * integrator from its kinetics library):
+     *   0  n_sub explicit Euler sub-steps,
+     *   1  n_sub linearly implicit (Rosenbrock) Euler sub-steps with the
+     *      analytic Jacobian of the rates at the sub-step's density,
+     *   2  explicit Euler with a per-cell count n = min(n_sub, max(1,
+     *      ceil(2 kappa))) of equal sub-steps, kappa the largest diagonal
+     *      entry |d f_i / d y_i| of that Jacobian at the cell's state      */
+    int32_t chem_scheme;
 } orc_setup;
 
 typedef struct orc_ctx orc_ctx;
@@ -100,7 +109,15 @@ void orc_lattice(int32_t dim, int32_t* c /* Q*3 */, double* w /* Q */);
 void orc_mixture(const orc_setup* s, double T, const double* Y,
                  double* mu, double* lam, double* rhoD);
 double orc_eos(const orc_setup* s, double T, const double* Y);
-/* 0-D isobaric reactor: nsteps time steps of n_sub explicit substeps each */
+/* production rates omega_k and heat release omega_T (Eqs. 8 and 9) */
+void orc_rates(const orc_setup* s, double T, const double* Y, double rho, double* wk,
+               double* wT);
+/* right-hand side of the reaction step at fixed density, f = (omega_k/rho,
+ * omega_T/(rho cp)) (ns + 1 values), and its Jacobian J[i][m] = d f_i/d y_m
+ * with y = (Y_1 .. Y_ns, T), row-major (ns + 1)^2 */
+void orc_rates_jacobian(const orc_setup* s, double T, const double* Y, double rho, double* f,
+                        double* J);
+/* 0-D isobaric reactor: nsteps time steps of the reaction step each */
 void orc_reactor(const orc_setup* s, double* T, double* Y, int32_t nsteps);
 /* fd phase alone with u forced to zero (conservation pin); writes T*, Y* */
 int  orc_fd_only(orc_ctx* o, double* Tstar, double* Ystar);

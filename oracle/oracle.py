@@ -44,7 +44,7 @@ class Setup(C.Structure):
         ("A", C.c_double * MAXR), ("beta", C.c_double * MAXR), ("theta", C.c_double * MAXR),
         ("rev", C.c_int32 * MAXR), ("lnKc_a", C.c_double * MAXR), ("lnKc_b", C.c_double * MAXR),
         ("closed", C.c_int32), ("r_gas", C.c_double), ("p0", C.c_double),
-        ("si", C.c_int32), ("outlet_sigma", C.c_double),
+        ("si", C.c_int32), ("outlet_sigma", C.c_double), ("chem_scheme", C.c_int32),
     ]
 
 
@@ -84,6 +84,8 @@ def lib():
         L.orc_eos.restype = C.c_double
         L.orc_eos.argtypes = [C.POINTER(Setup), C.c_double, dp]
         L.orc_reactor.argtypes = [C.POINTER(Setup), dp, dp, C.c_int32]
+        L.orc_rates.argtypes = [C.POINTER(Setup), C.c_double, dp, C.c_double, dp, dp]
+        L.orc_rates_jacobian.argtypes = [C.POINTER(Setup), C.c_double, dp, C.c_double, dp, dp]
         L.orc_fd_only.argtypes = [C.c_void_p, dp, dp]
         L.orc_p0.restype = C.c_double
         L.orc_p0.argtypes = [C.c_void_p]
@@ -131,6 +133,7 @@ def make_setup(s: dict) -> Setup:
     st.p0 = 1.0
     st.si = int(s.get("si", 0))
     st.outlet_sigma = float(s.get("outlet_sigma", 0.0))
+    st.chem_scheme = int(s.get("chem_scheme", 0))
     return st
 
 
@@ -252,8 +255,29 @@ def eos(setup, T, Y):
     return lib().orc_eos(C.byref(st), float(T), _dp(Yb))
 
 
+def rates(setup, T, Y, rho):
+    """Production rates omega_k and heat release omega_T (Eqs. 8 and 9)."""
+    st = make_setup(setup)
+    Yb = np.ascontiguousarray(np.asarray(Y, float))
+    wk = np.zeros(max(setup["ns"], 1))
+    wT = np.zeros(1)
+    lib().orc_rates(C.byref(st), float(T), _dp(Yb), float(rho), _dp(wk), _dp(wT))
+    return wk[: setup["ns"]], float(wT[0])
+
+
+def rates_jacobian(setup, T, Y, rho):
+    """f = (omega_k/rho, omega_T/(rho cp)) and J = df/dy, y = (Y, T), at fixed rho."""
+    st = make_setup(setup)
+    n = setup["ns"] + 1
+    Yb = np.ascontiguousarray(np.asarray(Y, float))
+    f = np.zeros(n)
+    J = np.zeros(n * n)
+    lib().orc_rates_jacobian(C.byref(st), float(T), _dp(Yb), float(rho), _dp(f), _dp(J))
+    return f, J.reshape(n, n)
+
+
 def reactor(setup, T, Y, nsteps):
-    """0-D isobaric reactor: nsteps steps of n_sub explicit sub-steps."""
+    """0-D isobaric reactor: nsteps steps of the reaction step (its scheme)."""
     st = make_setup(setup)
     Tb = np.array([float(T)])
     Yb = np.ascontiguousarray(np.asarray(Y, float).copy())

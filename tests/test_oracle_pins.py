@@ -1033,3 +1033,118 @@ def test_characteristic_outlet_settles_to_the_uniform_inflow():
     assert np.abs(f["Ph"]).max() <= 1e-7
     w = o.outlet_wave()
     assert np.abs(w + math.sqrt(CS2) * u_in).max() <= 1e-7
+
+
+# ------------------------------------------------- stiff reaction schemes
+
+def _fd_jacobian(s, T, Y, rho, eps=1e-6):
+    """Central differences of f = (omega_k/rho, omega_T/(rho cp)) at fixed rho,
+    from the rates alone (Eqs. 8 and 9)."""
+    ns = len(Y)
+    y0 = np.concatenate([Y, [T]])
+
+    def f(y):
+        wk, wT = O.rates(s, y[ns], y[:ns], rho)
+        return np.concatenate([wk / rho, [wT / (rho * s["cp"])]])
+
+    J = np.zeros((ns + 1, ns + 1))
+    for m in range(ns + 1):
+        h = eps * max(abs(y0[m]), 1e-3)
+        yp, ym = y0.copy(), y0.copy()
+        yp[m] += h
+        ym[m] -= h
+        J[:, m] = (f(yp) - f(ym)) / (2 * h)
+    return f(y0), J
+
+
+@pytest.mark.parametrize("mech", ["one_step", "synthetic9"])
+def test_reaction_jacobian_matches_finite_differences(mech):
+    """The analytic Jacobian of the reaction right-hand side at fixed density
+    (used by the linearly implicit scheme and the adaptive sub-step count)
+    against central differences of the rates: the nine-species mechanism
+    has unequal molar masses, reversible reactions with temperature-dependent
+    equilibrium constants and orders up to four."""
+    if mech == "one_step":
+        s = _reactor_setup(W.mech_one_step(A=W.one_step_rate_constant(tau_steps=5.0)),
+                           W.ONE_STEP_Y_IN)
+        Y = np.array([0.25, 0.35, 0.3, 0.1])
+        T = 1200.0
+    else:
+        s = _reactor_setup(W.mech_synthetic9(), W.SYNTH9_Y_IN)
+        rng = np.random.default_rng(9)
+        Y = rng.random(9) + 0.05
+        Y /= Y.sum()
+        T = 1500.0
+    rho = O.eos(s, T, Y)
+    f, J = O.rates_jacobian(s, T, Y, rho)
+    f_fd, J_fd = _fd_jacobian(s, T, Y, rho)
+    assert np.abs(f - f_fd).max() <= 1e-14 * np.abs(f).max()
+    scale = np.abs(J).max()
+    assert np.abs(J).max() > 0
+    assert np.abs(J - J_fd).max() <= 2e-7 * scale, np.abs(J - J_fd).max() / scale
+
+
+def _decay_setup(k, n_sub, scheme):
+    """A -> B, first order, no heat release (T and k stay fixed):
+    dY_A/dt = -k Y_A (the density cancels)."""
+    s = _mass_action_setup([2.0, 2.0], [1, 0], [0, 1], k, n_sub=n_sub, Y_in=[0.5, 0.5])
+    s["chem_scheme"] = scheme
+    return s
+
+
+@pytest.mark.parametrize("k,n_sub", [(0.3, 1), (50.0, 1), (50.0, 4)])
+def test_linearly_implicit_euler_on_linear_decay(k, n_sub):
+    """Linearly implicit (Rosenbrock) Euler on dY/dt = -k Y: each sub-step of
+    length h is Y <- Y / (1 + h k) exactly, so that a very stiff decay
+    (h k = 50, where explicit Euler diverges) decays monotonically."""
+    s = _decay_setup(k, n_sub, 1)
+    Y0 = np.array([0.8, 0.2])
+    for nsteps in (1, 7):
+        T1, Y1 = O.reactor(s, 1000.0, Y0, nsteps)
+        ref = 0.8 / (1.0 + k / n_sub) ** (n_sub * nsteps)
+        assert T1 == 1000.0
+        assert abs(Y1[0] - ref) <= 1e-15 + 1e-14 * ref
+        assert abs(Y1.sum() - 1.0) <= 1e-14
+    e = _decay_setup(k, n_sub, 0)
+    _, Ye = O.reactor(e, 1000.0, Y0, 7)
+    if k / n_sub > 2:
+        assert not abs(Ye[0]) <= 1.0  # explicit Euler: |1 - h k| > 1, diverges
+
+
+@pytest.mark.parametrize("k,n_max,n_expect", [(0.2, 8, 1), (1.3, 8, 3), (3.0, 4, 4)])
+def test_adaptive_substeps_on_linear_decay(k, n_max, n_expect):
+    """Per-cell adaptive explicit sub-steps: the stiffness is the largest
+    diagonal Jacobian entry, here |d f_A / d Y_A| = k, and the cell takes
+    n = min(n_max, max(1, ceil(2 k))) equal explicit sub-steps:
+    Y_A <- Y_A (1 - k/n)^n per step."""
+    s = _decay_setup(k, n_max, 2)
+    Y0 = np.array([0.8, 0.2])
+    _, Y1 = O.reactor(s, 1000.0, Y0, 3)
+    ref = 0.8 * (1.0 - k / n_expect) ** (3 * n_expect)
+    assert abs(Y1[0] - ref) <= 1e-15 + 1e-14 * ref
+
+
+def test_linearly_implicit_scheme_conserves_mass_and_reaches_equilibrium():
+    """Nine-species mechanism (mass-balanced reactions, unequal molar
+    masses): the species block of J has zero mass-weighted column sums, so
+    each linearly implicit sub-step keeps sum_k Y_k to round-off, and so
+    does the enthalpy cp T + sum_k dh_f,k Y_k.  A long run ends at chemical
+    equilibrium (f = 0), which fixes the state from those invariants alone:
+    the explicit scheme, run from the same start with sub-steps enough for
+    its stability (the adaptive count, up to 200), reaches the same one."""
+    s = _reactor_setup(W.mech_synthetic9(), W.SYNTH9_Y_IN, n_sub=1)
+    s["chem_scheme"] = 1
+    Y0 = np.array(W.SYNTH9_Y_IN, float)
+    dhf = np.array(s["mech"]["dhf"])
+    h0 = s["cp"] * 1400.0 + dhf @ Y0
+    T1, Y1 = O.reactor(s, 1400.0, Y0, 40)
+    assert abs(Y1.sum() - 1.0) <= 1e-14
+    assert abs(s["cp"] * T1 + dhf @ Y1 - h0) <= 1e-12 * abs(h0)
+    assert T1 > 1500.0  # the fresh mixture burns
+    T2, Y2 = O.reactor(s, T1, Y1, 20000)
+    f, _ = O.rates_jacobian(s, T2, Y2, O.eos(s, T2, Y2))
+    assert np.abs(f[:-1]).max() <= 1e-14
+    assert abs(Y2.sum() - 1.0) <= 1e-13
+    e = dict(s, chem_scheme=2, n_sub=200)
+    Te, Ye = O.reactor(e, 1400.0, Y0, 40000)
+    assert abs(Te - T2) <= 1e-9 * T2 and np.abs(Ye - Y2).max() <= 1e-9
