@@ -136,6 +136,21 @@ typedef struct {
                                         Dirichlet face temperatures and, from
                                         lbfd_init_state on, the initial state's
                                         maximum.  0: no bound beyond those           */
+    int32_t chem_scheme;             /* reaction step of one time step (after the
+                                        transport, Lie splitting; Eqs. 8, 9):
+                                        0: n_sub explicit Euler sub-steps;
+                                        1: n_sub linearly implicit (one-stage
+                                           Rosenbrock) Euler sub-steps with the
+                                           analytic Jacobian of the rates at the
+                                           sub-step's density: (I - h J) dy = h f
+                                           (no reaction bound in the stability
+                                           rule);
+                                        2: per cell, n = min(n_sub, max(1,
+                                           ceil(2 kappa))) explicit sub-steps,
+                                           kappa = max_i |J_ii| at the cell.
+                                        1 and 2 run in FP64 (in FP32 mode every
+                                        cell's reaction step goes to the FP64
+                                        island) and take at most 9 species.   */
     double outlet_sigma;             /* characteristic outlet: relaxation factor of
                                         the incoming wave (> 0; Poinsot and Lele
                                         suggest about 0.25); unused otherwise       */

@@ -55,6 +55,7 @@ struct Par {
     int nx, ny, nz, ns, nr;
     int n_lo, n_tab;  // reaction table segments (see Rxn)
     int n_sub, mu_model, transport, corr, any_beta;
+    int chem_scheme;  // 0 explicit, 1 linearly implicit Euler, 2 adaptive explicit
     int lb_bc[6], fd_bc[6];
     R A_u, A_T, inv_eta2, T_s, cp, inv_cp, inv_Pr, rho_in, T_in, mu_ref, S_T_in, S;
     R rho_ref;        // rho_in * T_in / Mbar_in  (EOS numerator), times P0 / P0_in
@@ -374,6 +375,203 @@ __device__ __forceinline__ void chem_increments(const Par<C>& P, C T0, const C* 
     }
 }
 
+// ---------------------------------------------- stiff reaction schemes
+// (FP64; species buckets up to 9.)  The right-hand side of the reaction step
+// at fixed density, f = (omega_k/rho, omega_T/(rho cp)), and its analytic
+// Jacobian J[i][m] = d f_i / d y_m, y = (Y_1 .. Y_NSM, T): by the law of mass
+// action, d Q_j / d[X_m] is the rate constant times the product of the other
+// factors of the side (each factor of the side in turn), d ln k_f / dT =
+// (beta + theta/T)/T and d ln k_r / dT = d ln k_f / dT + b/T^2; then
+// d f_k/d Y_m = (M_k/M_m) sum_j s_kj d Q_j/d[X_m], d f_k/dT = (M_k/rho)
+// sum_j s_kj d Q_j/dT and row T = -sum_k dh_f,k (row k) / cp.
+template <int NSM>
+__device__ __forceinline__ void rates_jacobian(const Par<double>& P, double T, const double* Y,
+                                               double rho, double* f,
+                                               double (&J)[NSM + 1][NSM + 1]) {
+    constexpr int N1 = NSM + 1;
+    double X[NSM + 1], w[NSM], GT[NSM], G[NSM][NSM];
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) {
+        X[k] = rho * Y[k] * P.invM[k];
+        w[k] = GT[k] = 0.0;
+#pragma unroll
+        for (int m = 0; m < NSM; ++m) G[k][m] = 0.0;
+    }
+    X[NSM] = 1.0;
+    const double invT = 1.0 / T;
+    const double lgT = P.any_beta ? flog(T) : 0.0;
+    const Rxn<double>& r = P.rx;
+    for (int j = 0; j < P.n_tab; ++j) {
+        const int nf = j < P.n_lo ? 2 : 4;
+        const double kf = r.A[j] * fexp(r.beta[j] * lgT - r.theta[j] * invT);
+        const double dlf = (r.beta[j] + r.theta[j] * invT) * invT;
+        const bool rv = r.rev[j] != 0;
+        const double kr = rv ? kf * fexp(-(r.lnKc_a[j] + r.lnKc_b[j] * invT)) : 0.0;
+        const double dlr = dlf + r.lnKc_b[j] * invT * invT;
+        int fi[4], ri[4];
+        double xf[4], xr[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            fi[q] = q < nf ? (int)((r.fidx[j] >> (8 * q)) & 255u) : NSM;
+            ri[q] = q < nf ? (int)((r.ridx[j] >> (8 * q)) & 255u) : NSM;
+            xf[q] = X[fi[q]];
+            xr[q] = X[ri[q]];
+        }
+        const double qf = kf * xf[0] * xf[1] * xf[2] * xf[3];
+        const double qr = kr * xr[0] * xr[1] * xr[2] * xr[3];
+        // d Q / d[X_m]: each factor q of a side contributes the product of the others
+        double df[4], dr[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double a = kf, b = kr;
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                if (o != q) {
+                    a *= xf[o];
+                    b *= xr[o];
+                }
+            df[q] = a;
+            dr[q] = b;
+        }
+        double dQ[NSM];
+#pragma unroll
+        for (int m = 0; m < NSM; ++m) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v += fi[q] == m ? df[q] : 0.0;
+                v -= ri[q] == m ? dr[q] : 0.0;
+            }
+            dQ[m] = v;
+        }
+        const double Qj = qf - qr, dQT = qf * dlf - qr * dlr;
+#pragma unroll
+        for (int k = 0; k < NSM; ++k) {
+            const double s = r.nud[j][k];
+            w[k] += s * Qj;
+            GT[k] += s * dQT;
+#pragma unroll
+            for (int m = 0; m < NSM; ++m) G[k][m] += s * dQ[m];
+        }
+    }
+    const double irho = 1.0 / rho;
+    double fT = 0.0;
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) {
+        f[k] = P.M[k] * w[k] * irho;
+        fT -= P.dhf[k] * f[k] * P.inv_cp;
+#pragma unroll
+        for (int m = 0; m < NSM; ++m) J[k][m] = P.M[k] * P.invM[m] * G[k][m];
+        J[k][NSM] = P.M[k] * irho * GT[k];
+    }
+    f[NSM] = fT;
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < NSM; ++k) v -= P.dhf[k] * J[k][m];
+        J[NSM][m] = v * P.inv_cp;
+    }
+}
+
+// A x = b by Gaussian elimination with partial pivoting, b overwritten with
+// x.  Every index is a compile-time constant after unrolling: the pivot row
+// is swapped in with selects.
+template <int n>
+__device__ __forceinline__ void solve_pivoted(double (&A)[n][n], double (&b)[n]) {
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        double best = fabs(A[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < n; ++r) {
+            const double v = fabs(A[r][c]);
+            if (v > best) {
+                best = v;
+                p = r;
+            }
+        }
+#pragma unroll
+        for (int r = c + 1; r < n; ++r) {
+            const bool sw = r == p;
+#pragma unroll
+            for (int q = c; q < n; ++q) {
+                const double t = A[c][q];
+                A[c][q] = sw ? A[r][q] : t;
+                A[r][q] = sw ? t : A[r][q];
+            }
+            const double t = b[c];
+            b[c] = sw ? b[r] : t;
+            b[r] = sw ? t : b[r];
+        }
+#pragma unroll
+        for (int r = c + 1; r < n; ++r) {
+            const double l = A[r][c] / A[c][c];
+#pragma unroll
+            for (int q = c; q < n; ++q) A[r][q] -= l * A[c][q];
+            b[r] -= l * b[c];
+        }
+    }
+#pragma unroll
+    for (int c = n - 1; c >= 0; --c) {
+        double v = b[c];
+#pragma unroll
+        for (int q = c + 1; q < n; ++q) v -= A[c][q] * b[q];
+        b[c] = v / A[c][c];
+    }
+}
+
+// The reaction step of one time step in FP64, by the parameters' scheme:
+//   0: n_sub explicit Euler sub-steps;
+//   1: n_sub linearly implicit (one-stage Rosenbrock) Euler sub-steps,
+//      (I - h J) dy = h f at the sub-step's state and density, y += dy;
+//   2: n = min(n_sub, max(1, ceil(2 kappa))) explicit sub-steps of length
+//      1/n, kappa = max_i |J_ii| at the cell's state.
+template <int NSM>
+__device__ __forceinline__ void chem_step(const Par<double>& P, double& T, double* Y) {
+    if constexpr (NSM > 0 && NSM <= 9) {
+        constexpr int N1 = NSM + 1;
+        if (P.chem_scheme == 1) {
+            const double h = P.h_sub;
+            for (int it = 0; it < P.n_sub; ++it) {
+                double J[N1][N1], b[N1];
+                rates_jacobian<NSM>(P, T, Y, eos<double, NSM>(P, T, Y), b, J);
+#pragma unroll
+                for (int i = 0; i < N1; ++i) {
+#pragma unroll
+                    for (int q = 0; q < N1; ++q) J[i][q] = -h * J[i][q];
+                    J[i][i] += 1.0;
+                    b[i] *= h;
+                }
+                solve_pivoted<N1>(J, b);
+#pragma unroll
+                for (int k = 0; k < NSM; ++k) Y[k] += b[k];
+                T += b[NSM];
+            }
+            return;
+        }
+        if (P.chem_scheme == 2) {
+            double J[N1][N1], f[N1], kap = 0.0;
+            rates_jacobian<NSM>(P, T, Y, eos<double, NSM>(P, T, Y), f, J);
+#pragma unroll
+            for (int i = 0; i < N1; ++i) kap = fmax(kap, fabs(J[i][i]));
+            const double m = ceil(2.0 * kap);
+            const int nsub = m < 1.0 ? 1 : m > (double)P.n_sub ? P.n_sub : (int)m;
+            const double h = 1.0 / nsub;
+            double wk[NSM], wT;
+            for (int it = 0; it < nsub; ++it) {
+                const double rho = eos<double, NSM>(P, T, Y);
+                rates<double, NSM>(P, T, Y, rho, wk, wT);
+#pragma unroll
+                for (int k = 0; k < NSM; ++k) Y[k] = Y[k] + h * wk[k] / rho;
+                T = T + h * wT / (rho * P.cp);
+            }
+            return;
+        }
+    }
+    chem_integrate<double, NSM>(P, T, Y);
+}
+
 // ------------------------------------------------------------ kernel args
 // Closed domain: P0 / P0_in = p = S0 / S with S = sum over cells of M / T (the
 // domain's mass is fixed and rho is proportional to P0 M / T).
@@ -410,6 +608,8 @@ struct StepArgs {
     int phase;            // PH_* mask
     int diag;             // write diagnostics partials
     int sur;              // FP32 surrogate mode: reactions left to the surrogate kernels
+    int stiff;            // stiff reaction scheme (chem_scheme 1 or 2): the FP64 step
+                          // and island kernels built with it
     // FP32 mode: compaction of the cells flagged for the FP64 reaction step
     int* gtot;            // [groups][GSPREAD] flagged cells per group of mask words (added
                           // by the kernels that write the masks, cleared by the island)

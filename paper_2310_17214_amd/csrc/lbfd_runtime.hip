@@ -388,7 +388,8 @@ lbfd_status stability_eval(const lbfd_grid& g, const lbfd_params& p, const HostM
         r.violated |= 8;
     if (!(r.tau_lo > 0.5 + 1e-3)) r.violated |= 1;
     if (!(r.fd_sum <= 0.9)) r.violated |= 2;
-    if (!(r.h_kappa <= 0.5)) r.violated |= 4;
+    // the linearly implicit scheme is stable at any h kappa: no reaction bound
+    if (!(r.h_kappa <= 0.5) && p.chem_scheme != 1) r.violated |= 4;
     if (!r.violated) return LBFD_OK;
     char buf[512];
     std::snprintf(buf, sizeof(buf),
@@ -412,6 +413,7 @@ Par<R> build_par(const lbfd_ctx* c) {
     P.ns = c->ns;
     P.nr = c->ns > 0 ? c->mech.nr : 0;
     P.n_sub = p.n_sub;
+    P.chem_scheme = p.chem_scheme;
     P.mu_model = p.mu_model;
     P.transport = p.transport_model;
     // temperature planes hold T - T_ref (FP32 mode: T_solid of the params the
@@ -769,6 +771,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.phase = phase;
     a.diag = 1;
     a.sur = sizeof(R) == 4 && c->sur && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM);
+    a.stiff = c->params.chem_scheme != 0;
     a.gtot = dptr<int>(c, c->L.gtot);
     a.list = dptr<int>(c, c->L.list);
     a.count = dptr<int>(c, c->L.count);
@@ -983,6 +986,10 @@ lbfd_status lbfd_set_params(lbfd_ctx* c, const lbfd_params* p) {
     if (p->transport_model != 0 && p->transport_model != 1)
         return fail(c, LBFD_E_INVAL, "transport_model");
     if (p->n_sub < 1 || p->n_sub > 4096) return fail(c, LBFD_E_INVAL, "n_sub must be 1..4096");
+    if (p->chem_scheme < 0 || p->chem_scheme > 2)
+        return fail(c, LBFD_E_INVAL, "chem_scheme must be 0, 1 or 2");
+    if (p->chem_scheme != 0 && c->nsm > 9)
+        return fail(c, LBFD_E_UNSUPPORTED, "stiff reaction schemes: at most 9 species");
     const double tau_in = p->nu_in * 3.0 + 0.5;
     if (!(tau_in > 0.5 + 1e-3)) return fail(c, LBFD_E_INVAL, "relaxation time at the inlet <= 0.501");
     const double uin = std::sqrt(p->u_in[0] * p->u_in[0] + p->u_in[1] * p->u_in[1] +

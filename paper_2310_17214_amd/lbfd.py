@@ -62,7 +62,8 @@ class Params(C.Structure):
                 ("fd_face", (C.c_double * (1 + MAX_SPECIES)) * 6),
                 ("n_sub", C.c_int32), ("ign_threshold", C.c_double),
                 ("closed", C.c_int32), ("r_gas", C.c_double), ("T_max", C.c_double),
-                ("outlet_sigma", C.c_double), ("sharp_interface", C.c_int32)]
+                ("chem_scheme", C.c_int32), ("outlet_sigma", C.c_double),
+                ("sharp_interface", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -189,6 +190,7 @@ def make_params(s: dict) -> Params:
     p.T_max = float(s.get("T_max", 0.0))
     p.sharp_interface = int(s.get("si", 0))
     p.outlet_sigma = float(s.get("outlet_sigma", 0.0))
+    p.chem_scheme = int(s.get("chem_scheme", 0))
     return p
 
 
