@@ -84,7 +84,10 @@ typedef enum {
 } lbfd_lb_bc;
 
 /* FD boundary kind per face; the +/- faces of an axis must both be periodic
- * or both non-periodic, and so must the LB kinds. */
+ * or both non-periodic, and so must the LB kinds.  An FD-periodic face needs
+ * an LB-periodic one; an LB-periodic face may instead carry an FD Dirichlet
+ * temperature (a thermal wall across which the flow is periodic: plug flow
+ * between isothermal walls), but no zero-gradient one. */
 typedef enum {
     LBFD_FD_PERIODIC = 0,
     LBFD_FD_DIRICHLET = 1,       /* cell-centred ghost at the face value           */

@@ -691,8 +691,11 @@ lbfd_status validate_grid(const lbfd_grid* g, std::string& msg) {
         if (lb < 0 || lb > 4 || fd < 0 || fd > 2) return msg = "unknown boundary kind", LBFD_E_INVAL;
         if (f >= nf && (lb != LBFD_LB_PERIODIC || fd != LBFD_FD_PERIODIC))
             return msg = "z faces of a 2-D grid must be periodic", LBFD_E_INVAL;
-        if ((lb == LBFD_LB_PERIODIC) != (fd == LBFD_FD_PERIODIC))
-            return msg = "LB and FD must agree on periodic faces", LBFD_E_INVAL;
+        if (fd == LBFD_FD_PERIODIC && lb != LBFD_LB_PERIODIC)
+            return msg = "an FD-periodic face needs an LB-periodic one", LBFD_E_INVAL;
+        if (lb == LBFD_LB_PERIODIC && fd == LBFD_FD_ZERO_GRADIENT)
+            return msg = "an LB-periodic face takes a periodic or Dirichlet FD kind",
+                   LBFD_E_INVAL;
         if (lb == LBFD_LB_VELOCITY_INLET && f != 0)
             return msg = "velocity inlet only on the -x face", LBFD_E_UNSUPPORTED;
         if ((lb == LBFD_LB_PRESSURE_OUTLET || lb == LBFD_LB_CHARACTERISTIC_OUTLET) && f != 1)
@@ -1027,6 +1030,11 @@ lbfd_status lbfd_set_params(lbfd_ctx* c, const lbfd_params* p) {
         return fail(c, LBFD_E_INVAL, "sharp_interface must be 0 or 1");
     if (p->sharp_interface && c->nsm > 4)
         return fail(c, LBFD_E_UNSUPPORTED, "sharp-interface mode: at most 4 species");
+    if (p->sharp_interface)
+        for (int f = 0; f < 6; ++f)
+            if ((c->grid.lb_bc[f] == LBFD_LB_PERIODIC) != (c->grid.fd_bc[f] == LBFD_FD_PERIODIC))
+                return fail(c, LBFD_E_UNSUPPORTED,
+                            "sharp-interface mode: LB and FD must agree on periodic faces");
     if (p->sharp_interface && c->sur)
         return fail(c, LBFD_E_UNSUPPORTED,
                     "sharp-interface mode runs the exact reaction step (surrogate set)");

@@ -1148,3 +1148,32 @@ def test_linearly_implicit_scheme_conserves_mass_and_reaches_equilibrium():
     e = dict(s, chem_scheme=2, n_sub=200)
     Te, Ye = O.reactor(e, 1400.0, Y0, 40000)
     assert abs(Te - T2) <= 1e-9 * T2 and np.abs(Ye - Y2).max() <= 1e-9
+
+
+# ----------------------------------------------- Graetz (plug flow, Sec. 4.3)
+
+def test_plug_flow_thermal_entrance_matches_the_exact_discrete_solution():
+    """Uniform flow between isothermal walls (FD Dirichlet on LB-periodic
+    faces), inflow at T_in: the steady temperature is the exact solution of
+    the discrete upwind/central equations -- discrete sine modes across the
+    channel, each decaying geometrically along x with the root below one of
+    alpha r^2 - (2 alpha + alpha kappa_n + U) r + (alpha + U) = 0 -- up to
+    the columns next to the zero-gradient outlet.  A wrong diffusion
+    coefficient, upwind direction or ghost position changes the roots or
+    the coefficients."""
+    from paper_2310_17214_amd import graetz as G
+
+    ny = 7
+    s, alpha = G.setup(ny, Pe=20.0, dT=1e-4)
+    shape = (1, ny, s["nx"])
+    o = O.Oracle(s, np.zeros(shape))
+    u0 = np.zeros((2,) + shape)
+    u0[0] = s["u_in"][0]
+    o.init_state(np.full(shape, s["T_in"]), None, u0)
+    o.step(20000)
+    T_w = s["fd_val"][2][0]
+    That = (T_w - o.read(O.F_T)[0]) / (T_w - s["T_in"])
+    disc = G.discrete_solution(s["nx"], ny, alpha, s["u_in"][0])
+    assert np.abs(That[:, :-10] - disc[:, :-10]).max() <= 2e-7
+    # and it lies close to the paper's continuous series (first-order upwind)
+    assert G.section_mse(That, s, alpha, 1.0) < 1e-3
