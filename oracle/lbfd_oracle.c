@@ -131,6 +131,14 @@ static double closed_sum(const orc_ctx* o) {
 
 /* Sutherland law (Sec. 4, Eq. muT) written as a ratio to the inlet state so
  * that the reference temperature cancels: mu(T)/mu(T_in).                   */
+/* Mixture heat capacity, c_p = sum_k Y_k c_p,k (cp when the species share it). */
+static double cp_of(const orc_setup* s, const double* Y) {
+    if (!s->cpk) return s->cp;
+    double c = 0.0;
+    for (int k = 0; k < s->ns; ++k) c += Y[k] * s->cp_k[k];
+    return c;
+}
+
 static double sutherland_ratio(const orc_setup* s, double T) {
     if (s->mu_model == 0) return 1.0;
     double x = T / s->T_in;
@@ -144,24 +152,25 @@ static double wilke_phi(double mu_k, double mu_j, double M_k, double M_j) {
 }
 
 /* Transport properties of one state.
- * single gas: mu from Sutherland, lambda = mu cp/Pr (Eq. lambdaT).
- * mixture:    mu_k = mu*_k mu_ref s(T), lambda_k = mu_k cp/Pr, mixed by
+ * single gas: mu from Sutherland, lambda = mu c_p/Pr (Eq. lambdaT) with the
+ *             mixture c_p.
+ * mixture:    mu_k = mu*_k mu_ref s(T), lambda_k = mu_k c_p,k/Pr, mixed by
  *             Eqs. muT_mix and conduct_mix with X_k = Y_k M/M_k.
  * Species diffusivity (constant-Lewis closure of j_k = -rho D_k grad Y_k):
- *             rho D_k = lambda/(cp Le_k).                                     */
+ *             rho D_k = lambda/(c_p Le_k), c_p of the mixture.               */
 static void mixture(const orc_setup* s, const double Phi[ORC_MAXS][ORC_MAXS], double T,
                     const double* Y, double* mu, double* lam, double* rhoD) {
     double mu0 = s->rho_in * s->nu_in * sutherland_ratio(s, T);
     if (s->transport == 0 || s->ns == 0) {
         *mu = mu0;
-        *lam = mu0 * s->cp / s->Pr;
+        *lam = mu0 * cp_of(s, Y) / s->Pr;
     } else {
         double X[ORC_MAXS], mbar = 1.0 / inv_mbar(s, Y);
         for (int k = 0; k < s->ns; ++k) X[k] = Y[k] * mbar / s->M[k];
         double m = 0.0, l1 = 0.0, l2 = 0.0;
         for (int k = 0; k < s->ns; ++k) {
             double muk = s->mu_star[k] * mu0;
-            double lamk = muk * s->cp / s->Pr;
+            double lamk = muk * (s->cpk ? s->cp_k[k] : s->cp) / s->Pr;
             double den = 0.0;
             for (int j = 0; j < s->ns; ++j) den += Phi[k][j] * X[j];
             m += muk * X[k] / den;
@@ -171,8 +180,10 @@ static void mixture(const orc_setup* s, const double Phi[ORC_MAXS][ORC_MAXS], do
         *mu = m;
         *lam = 0.5 * (l1 + 1.0 / l2);
     }
-    if (rhoD)
-        for (int k = 0; k < s->ns; ++k) rhoD[k] = *lam / (s->cp * s->Le[k]);
+    if (rhoD) {
+        double cp = cp_of(s, Y);
+        for (int k = 0; k < s->ns; ++k) rhoD[k] = *lam / (cp * s->Le[k]);
+    }
 }
 
 static void build_phi(const orc_setup* s, double Phi[ORC_MAXS][ORC_MAXS]) {
@@ -478,7 +489,7 @@ static void fd_cell(const orc_ctx* o, int x, int y, int z, const double* u, doub
     double H = s->A_T * lam_c * phif * phis * phis / (s->eta * s->eta);
     if (s->si) H = 0.0; /* SI mode: no interface heat exchange */
 
-    double advT = 0.0, lapT = 0.0, advY[ORC_MAXS], J[ORC_MAXS];
+    double advT = 0.0, lapT = 0.0, advY[ORC_MAXS], J[ORC_MAXS], cpj = 0.0;
     for (int k = 0; k < ns; ++k) advY[k] = J[k] = 0.0;
     for (int a = 0; a < s->dim; ++a) {
         int dx = a == 0, dy = a == 1, dz = a == 2;
@@ -487,6 +498,23 @@ static void fd_cell(const orc_ctx* o, int x, int y, int z, const double* u, doub
         state_at(o, x + dx, y + dy, z + dz, x, y, z, &Tp, Yp);
         double up = u[a] > 0.0 ? u[a] : 0.0, un = u[a] < 0.0 ? u[a] : 0.0;
         advT += up * (Tc - Tm) + un * (Tp - Tc);
+        if (s->cpk) {
+            /* species heat flux (sum_k c_p,k j_k) . grad T with the cell's
+             * diffusive fluxes j_k = -rho D_k dY_k (plus the correction
+             * velocity's Y_k sum_m rho D_m dY_m for unequal Lewis numbers),
+             * central differences over the two neighbours (ghosts included) */
+            double gT = 0.5 * (Tp - Tm), gY[ORC_MAXS], sum = 0.0, f = 0.0;
+            for (int k = 0; k < ns; ++k) {
+                gY[k] = 0.5 * (Yp[k] - Ym[k]);
+                sum += rD_c[k] * gY[k];
+            }
+            for (int k = 0; k < ns; ++k) {
+                double jk = -rD_c[k] * gY[k];
+                if (o->corr) jk += Yc[k] * sum;
+                f += s->cp_k[k] * jk;
+            }
+            cpj += f * gT;
+        }
         for (int k = 0; k < ns; ++k) advY[k] += up * (Yc[k] - Ym[k]) + un * (Yp[k] - Yc[k]);
         for (int side = 0; side < 2; ++side) {
             double Tn = side == 0 ? Tm : Tp;
@@ -507,14 +535,15 @@ static void fd_cell(const orc_ctx* o, int x, int y, int z, const double* u, doub
             }
         }
     }
-    double qT = (lapT + H * (s->T_s - Tc)) / (rho_c * s->cp);
+    double cp_c = cp_of(s, Yc);
+    double qT = (lapT + H * (s->T_s - Tc) - cpj) / (rho_c * cp_c);
     double dlnp = 0.0;
     if (s->closed) {
         /* dP0/dt (Eq. energy-transport-DI-version), explicit: the change of
          * P0 over the previous step, P0_in (p^n - p^{n-1}) per unit time */
         const double mbar_in = ns ? 1.0 / inv_mbar(s, s->Y_in) : 1.0;
         const double P0_in = s->rho_in * s->r_gas * s->T_in / mbar_in;
-        qT += P0_in * (s->p0 - o->p_prev) / (rho_c * s->cp);
+        qT += P0_in * (s->p0 - o->p_prev) / (rho_c * cp_c);
         dlnp = (s->p0 - o->p_prev) / s->p0;
     }
     *Tout = Tc + (qT - advT);
@@ -646,11 +675,11 @@ void orc_rates_jacobian(const orc_setup* s, double T, const double* Y, double rh
             for (int m = 0; m < ns; ++m) G[k][m] += skj * dQ[m];
         }
     }
-    double fT = 0.0;
+    double fT = 0.0, cp = cp_of(s, Y); /* c_p held at the state's, like rho */
     for (int i = 0; i < n * n; ++i) J[i] = 0.0;
     for (int k = 0; k < ns; ++k) {
         f[k] = s->M[k] * w[k] / rho;
-        fT -= s->dhf[k] * f[k] / s->cp;
+        fT -= s->dhf[k] * f[k] / cp;
         for (int m = 0; m < ns; ++m) J[k * n + m] = s->M[k] / s->M[m] * G[k][m];
         J[k * n + ns] = s->M[k] / rho * GT[k];
     }
@@ -658,7 +687,7 @@ void orc_rates_jacobian(const orc_setup* s, double T, const double* Y, double rh
     for (int m = 0; m < n; ++m) {
         double v = 0.0;
         for (int k = 0; k < ns; ++k) v -= s->dhf[k] * J[k * n + m];
-        J[ns * n + m] = v / s->cp;
+        J[ns * n + m] = v / cp;
     }
 }
 
@@ -737,10 +766,10 @@ static void chem_integrate(const orc_setup* s, double* T, double* Y) {
     }
     double h = 1.0 / nsub;
     for (int it = 0; it < nsub; ++it) {
-        double rho = orc_eos(s, *T, Y);
+        double rho = orc_eos(s, *T, Y), cp = cp_of(s, Y);
         rates(s, *T, Y, rho, wk, &wT);
         for (int k = 0; k < s->ns; ++k) Y[k] = Y[k] + h * wk[k] / rho;
-        *T = *T + h * wT / (rho * s->cp);
+        *T = *T + h * wT / (rho * cp);
     }
 }
 
@@ -785,7 +814,7 @@ static void reduce_phase(orc_ctx* o, int count) {
         double Y[ORC_MAXS], T = o->T[id];
         for (int k = 0; k < s->ns; ++k) Y[k] = o->Y[(long)k * o->N + id];
         double rho = orc_eos(s, T, Y);
-        double hsum = s->cp * T;
+        double hsum = cp_of(s, Y) * T;
         int bad = !isfinite(T), neg = 0;
         for (int k = 0; k < s->ns; ++k) {
             sp[k] += rho * Y[k];

@@ -82,6 +82,14 @@ typedef struct {
      *      ceil(2 kappa))) of equal sub-steps, kappa the largest diagonal
      *      entry |d f_i / d y_i| of that Jacobian at the cell's state      */
     int32_t chem_scheme;
+    /* species heat capacities c_p,k (Sec. 3.3, Eq. energy-transport-DI-
+     * version): with cpk = 1 the mixture has c_p = sum_k Y_k c_p,k (in the
+     * temperature equation, lambda = mu c_p/Pr, rho D_k = lambda/(c_p Le_k),
+     * the reaction step and the enthalpy) and the temperature equation gets
+     * the species heat-flux term -(sum_k c_p,k j_k) . grad T; cpk = 0: every
+     * species at cp */
+    int32_t cpk;
+    double  cp_k[ORC_MAXS];
 } orc_setup;
 
 typedef struct orc_ctx orc_ctx;

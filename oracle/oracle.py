@@ -45,6 +45,7 @@ class Setup(C.Structure):
         ("rev", C.c_int32 * MAXR), ("lnKc_a", C.c_double * MAXR), ("lnKc_b", C.c_double * MAXR),
         ("closed", C.c_int32), ("r_gas", C.c_double), ("p0", C.c_double),
         ("si", C.c_int32), ("outlet_sigma", C.c_double), ("chem_scheme", C.c_int32),
+        ("cpk", C.c_int32), ("cp_k", C.c_double * MAXS),
     ]
 
 
@@ -134,6 +135,11 @@ def make_setup(s: dict) -> Setup:
     st.si = int(s.get("si", 0))
     st.outlet_sigma = float(s.get("outlet_sigma", 0.0))
     st.chem_scheme = int(s.get("chem_scheme", 0))
+    cpk = mech.get("cp")
+    st.cpk = 1 if cpk is not None else 0
+    if cpk is not None:
+        for k in range(ns):
+            st.cp_k[k] = float(cpk[k])
     return st
 
 

@@ -1177,3 +1177,101 @@ def test_plug_flow_thermal_entrance_matches_the_exact_discrete_solution():
     assert np.abs(That[:, :-10] - disc[:, :-10]).max() <= 2e-7
     # and it lies close to the paper's continuous series (first-order upwind)
     assert G.section_mse(That, s, alpha, 1.0) < 1e-3
+
+
+# ------------------------------------------- species heat capacities c_p,k
+
+def test_species_heat_flux_term_gives_the_exact_discrete_exponential_profile():
+    """Sec. 3.3, Eq. energy-transport-DI-version with species heat capacities:
+    the temperature equation gets -(sum_k c_p,k j_k) . grad T.  Three inert
+    species (equal molar masses) between two Dirichlet faces, constant
+    viscosity, with c_p,k = c_p (1, 1.5, 2), Le_k = (1, 2/3, 1/2) and face
+    compositions whose difference g = (0.2, -0.4, 0.2) has sum_k g_k =
+    sum_k c_p,k g_k = sum_k g_k / Le_k = 0: the mixture c_p, lambda and every
+    rho D_k are then uniform, the correction flux vanishes, the steady
+    mass fractions are linear, and the steady temperature solves
+    lambda (T_{i+1} - 2 T_i + T_{i-1}) + B (T_{i+1} - T_{i-1})/2 = 0 with
+    B = sum_k c_p,k rho D_k g_k / (n + 1): T_i = A + C r^(i+1), r =
+    (lambda - B/2)/(lambda + B/2).  Without the term the profile is linear;
+    with the wrong sign or factor r moves."""
+    nx = 10
+    s = W.base_setup(2, nx, 1, 1, 3)
+    s["lb_bc"] = ["wall", "wall", "periodic", "periodic", "periodic", "periodic"]
+    s["fd_bc"] = ["dirichlet", "dirichlet", "periodic", "periodic", "periodic", "periodic"]
+    YL, YR = [0.2, 0.5, 0.3], [0.4, 0.1, 0.5]
+    TL, TR = 300.0, 420.0
+    s["fd_val"][0] = [TL] + YL
+    s["fd_val"][1] = [TR] + YR
+    s["mu_model"] = 0
+    s["nu_in"] = 0.1
+    s["Le"] = [1.0, 2.0 / 3.0, 0.5]
+    s["Y_in"] = YL
+    cp0 = s["cp"]
+    s["mech"] = dict(W.mech_empty(3), cp=[cp0, 1.5 * cp0, 2.0 * cp0])
+    shape = (1, 1, nx)
+    o = O.Oracle(s, np.zeros(shape))
+    x = np.arange(nx)
+    Y0 = np.stack([np.full(shape, 0.3), np.full(shape, 0.3), np.full(shape, 0.4)])
+    o.init_state(np.full(shape, 350.0), Y0)
+    o.step(20000)
+    f = o.fields()
+    T = f["T"][0, 0]
+    g = np.array(YR) - np.array(YL)
+    Ylin = np.array(YL)[:, None] + g[:, None] * (x + 1) / (nx + 1)
+    assert np.abs(f["Y"][:, 0, 0, :] - Ylin).max() <= 1e-12
+    mu = s["rho_in"] * s["nu_in"]
+    cpm = cp0 * (0.2 * 1 + 0.5 * 1.5 + 0.3 * 2)
+    lam = mu * cpm / s["Pr"]
+    rD = mu / (s["Pr"] * np.array(s["Le"]))
+    B = float(np.sum(cp0 * np.array([1.0, 1.5, 2.0]) * rD * g)) / (nx + 1)
+    r = (lam - B / 2) / (lam + B / 2)
+    C = (TR - TL) / (r ** (nx + 1) - 1.0)
+    A = TL - C
+    ref = A + C * r ** (x + 1)
+    assert abs(B) > 1e-4 * lam  # the term matters here
+    assert np.abs(T - ref).max() <= 1e-10 * TR
+    lin = TL + (TR - TL) * (x + 1) / (nx + 1)
+    assert np.abs(T - lin).max() > 0.5  # visibly not the linear profile (0.96 K)
+
+
+def test_equal_species_heat_capacities_reduce_to_the_single_cp_model():
+    """c_p,k all equal to c_p: sum_k c_p,k j_k = c_p sum_k j_k = 0, and the
+    mixture c_p is c_p: the run equals the single-c_p one to round-off."""
+    s, phi, T0, Y0, u0 = _cpk_box()
+    a = O.Oracle(s, phi)
+    b = O.Oracle(dict(s, mech=dict(s["mech"], cp=[s["cp"]] * 4)), phi)
+    for o in (a, b):
+        o.init_state(T0, Y0, u0)
+        o.step(40)
+    fa, fb = a.fields(), b.fields()
+    for k in ("T", "Y", "u"):
+        assert np.abs(fa[k] - fb[k]).max() <= 1e-12 * max(np.abs(fa[k]).max(), 1e-300), k
+
+
+def _cpk_box():
+    from setups import small_box
+
+    return small_box()
+
+
+def test_reaction_step_with_species_heat_capacities_closed_form():
+    """A -> B, heat of formation Q of A, c_p,A != c_p,B, no transport: with
+    Eq. 9 the temperature follows c_p(Y) dT = -Q dY_B... i.e.
+    dT/dY_A = -Q / c_p(Y_A), c_p = c_B + (c_A - c_B) Y_A, so complete
+    conversion ends at T0 + Q/(c_A - c_B) ln(c_p(Y_A0)/c_B); the explicit
+    sub-steps converge to it at first order."""
+    cA, cB, Q = 1.0, 1.6, 500.0
+    mech = dict(M=[1.0, 1.0], dhf=[Q, 0.0], mu_star=[1.0, 1.0], nu_f=[[1, 0]], nu_r=[[0, 1]],
+                A=[0.5], beta=[0.0], theta=[0.0], rev=[0], lnKc_a=[0.0], lnKc_b=[0.0],
+                cp=[cA, cB])
+    Y0 = np.array([0.7, 0.3])
+    ref = 400.0 + Q / (cA - cB) * math.log((cB + (cA - cB) * Y0[0]) / cB)
+    errs = []
+    for n_sub in (50, 100):
+        s = _reactor_setup(mech, [0.5, 0.5], n_sub=n_sub)
+        T1, Y1 = O.reactor(s, 400.0, Y0, 80)
+        assert Y1[0] < 1e-12
+        errs.append(abs(T1 - ref))
+    assert errs[0] < 0.5 and 1.8 < errs[0] / errs[1] < 2.2, errs
+    const = 400.0 + Q * Y0[0] / cA  # what a single c_p would give
+    assert abs(const - ref) > 10.0
