@@ -188,6 +188,18 @@ typedef struct {
     const int32_t* reversible;/* [nr] 0/1; k_r = k_f / exp(lnKc_a + lnKc_b/T)     */
     const double* lnKc_a;     /* [nr]                                             */
     const double* lnKc_b;     /* [nr]                                             */
+    const double* cp;         /* [ns] species heat capacities c_p,k in the units of
+                                 params.cp, or NULL (every species at params.cp).
+                                 Given, the mixture has c_p = sum_k Y_k c_p,k (in
+                                 the temperature equation, lambda = mu c_p/Pr,
+                                 rho D_k = lambda/(c_p Le_k), the reaction step
+                                 and the enthalpy) and the temperature equation
+                                 gets the species heat-flux term
+                                 -(sum_k c_p,k j_k) . grad T (Sec. 3.3, Eq.
+                                 energy-transport-DI-version).  Single-gas
+                                 transport, the explicit reaction scheme, no
+                                 surrogate, no sharp-interface mode, at most 9
+                                 species (LBFD_E_UNSUPPORTED otherwise)       */
 } lbfd_mechanism;
 
 typedef struct {

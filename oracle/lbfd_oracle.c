@@ -790,7 +790,7 @@ static void chem_phase(orc_ctx* o, int do_chem) {
         if (do_chem && s->ns > 0 && s->nr > 0 && !is_solid(o, id)) {
             double wk[ORC_MAXS], wT, rho = orc_eos(s, T, Y);
             rates(s, T, Y, rho, wk, &wT);
-            if (fabs(wT) / (rho * s->cp) > s->theta_ign) flagged++;
+            if (fabs(wT) / (rho * cp_of(s, Y)) > s->theta_ign) flagged++;
             chem_integrate(s, &T, Y);
         }
         o->divu[id] = o->qT[id] + (T - T0) / T0;

@@ -77,7 +77,10 @@ struct Par {
     R K_out;          // its relaxation factor sigma c_s (1 - Ma^2) / nx
     R c_s;            // sqrt(1/3), rounded once on the host
     R fd_face[6][1 + MAXS];  // Dirichlet face values: T - T_ref, then Y_k
-    R rD_fac[MAXS];   // 1/(cp Le_k)
+    R rD_fac[MAXS];   // 1/(cp Le_k); with species heat capacities 1/Le_k (rho D_k =
+                      // lambda/(c_p Le_k) with the cell's mixture c_p)
+    int cpk;          // species heat capacities given (c_p = sum_k Y_k c_p,k)
+    R cp_k[MAXS];     // c_p,k (0 for padding species)
     R M[MAXS], invM[MAXS], dhf[MAXS], mu_star[MAXS];
     R inv_mu_star[MAXS];  // 1 / mu_star (mu_star = 1 for padding species)
     R Pr_over_cp;         // Pr / cp
@@ -197,8 +200,20 @@ __device__ __forceinline__ R sutherland(const Par<R>& P, R T) {
     return dvd(x * fsqrt(x) * P.S_T_in, T + P.S);
 }
 
-// Viscosity and conductivity of one state (single gas or Wilke mixture).
+// Mixture heat capacity c_p = sum_k Y_k c_p,k (kernels built with species
+// heat capacities only).
 template <typename R, int NSM>
+__device__ __forceinline__ R cp_mix(const Par<R>& P, const R* Y) {
+    R c = R(0);
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) c += Y[k] * P.cp_k[k];
+    return c;
+}
+
+// Viscosity and conductivity of one state (single gas or Wilke mixture).
+// CPK: species heat capacities, lambda = mu c_p/Pr with the mixture c_p
+// (single gas only; the runtime refuses them with the Wilke closure).
+template <typename R, int NSM, bool CPK = false>
 __device__ __forceinline__ void transport(const Par<R>& P, R T, const R* Y, R& mu, R& lam) {
     R mu0 = P.mu_ref * sutherland(P, T);
     if constexpr (NSM > 0) {
@@ -237,7 +252,10 @@ __device__ __forceinline__ void transport(const Par<R>& P, R T, const R* Y, R& m
         }
     }
     mu = mu0;
-    lam = mu0 * P.cp * P.inv_Pr;
+    if constexpr (CPK && NSM > 0)
+        lam = mu0 * cp_mix<R, NSM>(P, Y) * P.inv_Pr;
+    else
+        lam = mu0 * P.cp * P.inv_Pr;
 }
 
 // e_i = c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2) with cs2 = 1/3
@@ -329,23 +347,34 @@ __device__ __forceinline__ void rates(const Par<C>& P, C T, const C* Y, C rho, C
     wT = w;
 }
 
+// 1 / c_p of a state: the mixture's with species heat capacities (CPK), the
+// parameter otherwise.
+template <typename C, int NSM, bool CPK>
+__device__ __forceinline__ C inv_cp_of(const Par<C>& P, const C* Y) {
+    if constexpr (CPK && NSM > 0)
+        return C(1) / cp_mix<C, NSM>(P, Y);
+    else
+        return P.inv_cp;
+}
+
 // One explicit Euler sub-step from rates already evaluated at (T, Y, rho).
-template <typename C, int NSM>
+template <typename C, int NSM, bool CPK = false>
 __device__ __forceinline__ void chem_apply(const Par<C>& P, C& T, C* Y, C rho, const C* wk, C wT) {
     const C hr = P.h_sub * rcp(rho);
+    const C icp = inv_cp_of<C, NSM, CPK>(P, Y);
 #pragma unroll
     for (int k = 0; k < NSM; ++k) Y[k] = Y[k] + hr * wk[k];
-    T = T + hr * wT * P.inv_cp;
+    T = T + hr * wT * icp;
 }
 
 // n_sub explicit Euler sub-steps at constant pressure, in type C.
-template <typename C, int NSM>
+template <typename C, int NSM, bool CPK = false>
 __device__ __forceinline__ void chem_integrate(const Par<C>& P, C& T, C* Y) {
     C wk[LBFD_NA(NSM)], wT;
     for (int n = 0; n < P.n_sub; ++n) {
         const C rho = eos<C, NSM>(P, T, Y);
         rates<C, NSM>(P, T, Y, rho, wk, wT);
-        chem_apply<C, NSM>(P, T, Y, rho, wk, wT);
+        chem_apply<C, NSM, CPK>(P, T, Y, rho, wk, wT);
     }
 }
 
@@ -354,13 +383,13 @@ __device__ __forceinline__ void chem_integrate(const Par<C>& P, C& T, C* Y) {
 // increments at full precision (in FP32 the chemical heat release of a slow
 // cell is far below the rounding unit of T).  `wk`, `wT` and `rho0` hold the
 // rates already evaluated at the base state.
-template <typename C, int NSM>
+template <typename C, int NSM, bool CPK = false>
 __device__ __forceinline__ void chem_increments(const Par<C>& P, C T0, const C* Y0, C rho0,
                                                 const C* wk0, C wT0, C& dT, C* dY) {
     C hr = P.h_sub * rcp(rho0);
 #pragma unroll
     for (int k = 0; k < NSM; ++k) dY[k] = hr * wk0[k];
-    dT = hr * wT0 * P.inv_cp;
+    dT = hr * wT0 * inv_cp_of<C, NSM, CPK>(P, Y0);
     C wk[LBFD_NA(NSM)], wT, Y[LBFD_NA(NSM)];
     for (int n = 1; n < P.n_sub; ++n) {
         const C T = T0 + dT;
@@ -369,9 +398,10 @@ __device__ __forceinline__ void chem_increments(const Par<C>& P, C T0, const C* 
         const C rho = eos<C, NSM>(P, T, Y);
         rates<C, NSM>(P, T, Y, rho, wk, wT);
         hr = P.h_sub * rcp(rho);
+        const C icp = inv_cp_of<C, NSM, CPK>(P, Y);
 #pragma unroll
         for (int k = 0; k < NSM; ++k) dY[k] = dY[k] + hr * wk[k];
-        dT = dT + hr * wT * P.inv_cp;
+        dT = dT + hr * wT * icp;
     }
 }
 
@@ -610,6 +640,7 @@ struct StepArgs {
     int sur;              // FP32 surrogate mode: reactions left to the surrogate kernels
     int stiff;            // stiff reaction scheme (chem_scheme 1 or 2): the FP64 step
                           // and island kernels built with it
+    int cpk;              // species heat capacities: the kernels built with them
     // FP32 mode: compaction of the cells flagged for the FP64 reaction step
     int* gtot;            // [groups][GSPREAD] flagged cells per group of mask words (added
                           // by the kernels that write the masks, cleared by the island)

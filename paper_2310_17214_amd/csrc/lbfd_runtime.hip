@@ -26,6 +26,7 @@ struct HostMech {
     int ns = 0, nr = 0;
     std::vector<double> M, dhf, mu_star, A, beta, theta, lnKc_a, lnKc_b;
     std::vector<int> nu_f, nu_r, rev;
+    std::vector<double> cp;  // species heat capacities (empty: all at params.cp)
 };
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -265,6 +266,11 @@ lbfd_status mech_from_abi(const lbfd_mechanism* m, HostMech& h, std::string& msg
         h.M.push_back(m->M[k]);
         h.dhf.push_back(m->dhf[k]);
         h.mu_star.push_back(m->mu_star[k]);
+        if (m->cp) {
+            if (!(m->cp[k] > 0.0) || !std::isfinite(m->cp[k]))
+                return msg = "species heat capacities must be positive", LBFD_E_INVAL;
+            h.cp.push_back(m->cp[k]);
+        }
     }
     for (int j = 0; j < nr; ++j) {
         if (!(m->A[j] >= 0.0) || !std::isfinite(m->A[j]) || !std::isfinite(m->beta[j]) ||
@@ -470,7 +476,10 @@ Par<R> build_par(const lbfd_ctx* c) {
     double im_in = 0.0;
     int corr = 0;
     for (int k = 0; k < c->ns; ++k) {
-        P.rD_fac[k] = (R)(1.0 / (p.cp * p.Le[k]));
+        // with species heat capacities rho D_k = (lambda / c_p) / Le_k, the
+        // mixture c_p taken per cell
+        P.rD_fac[k] = c->mech.cp.empty() ? (R)(1.0 / (p.cp * p.Le[k])) : (R)(1.0 / p.Le[k]);
+        P.cp_k[k] = c->mech.cp.empty() ? (R)p.cp : (R)c->mech.cp[k];
         if (p.Le[k] != p.Le[0]) corr = 1;
         P.M[k] = (R)c->mech.M[k];
         P.invM[k] = (R)(1.0 / c->mech.M[k]);
@@ -479,6 +488,7 @@ Par<R> build_par(const lbfd_ctx* c) {
         im_in += p.Y_in[k] / c->mech.M[k];
     }
     P.corr = corr;
+    P.cpk = c->ns > 0 && !c->mech.cp.empty();
     P.any_beta = 0;
     for (int j = 0; j < P.nr; ++j)
         if (c->mech.beta[j] != 0.0) P.any_beta = 1;
@@ -552,6 +562,22 @@ bool ready_for_tables(const lbfd_ctx* c) { return c->have_params && (c->ns == 0 
 // The stability rule for a context with the given params and mechanism, over
 // the temperatures of the initial state when one was set.
 lbfd_status check_stable(lbfd_ctx* c, const lbfd_params& p, const HostMech* m) {
+    if (m && !m->cp.empty()) {  // what the kernels with species heat capacities cover
+        if (p.transport_model != 0)
+            return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: single-gas transport only");
+        if (p.chem_scheme != 0)
+            return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: explicit reaction scheme only");
+        if (p.sharp_interface)
+            return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: no sharp-interface mode");
+        if (c->nsm > 9)
+            return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: at most 9 species");
+        if (c->sur)
+            return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: no surrogate");
+        if (p.closed)
+            for (double v : m->cp)
+                if (!(p.r_gas < v))
+                    return fail(c, LBFD_E_INVAL, "closed domain: r_gas below every c_p,k");
+    }
     lbfd_stability_report r;
     std::string msg;
     const lbfd_status st = stability_eval(c->grid, p, m, c->have_state ? c->state_T[0] : 0.0,
@@ -775,6 +801,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.diag = 1;
     a.sur = sizeof(R) == 4 && c->sur && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM);
     a.stiff = c->params.chem_scheme != 0;
+    a.cpk = c->ns > 0 && !c->mech.cp.empty();
     a.gtot = dptr<int>(c, c->L.gtot);
     a.list = dptr<int>(c, c->L.list);
     a.count = dptr<int>(c, c->L.count);
@@ -1428,6 +1455,8 @@ lbfd_status lbfd_set_surrogate(lbfd_ctx* c, const float* w, const float* norm, c
     if (c->have_params && c->params.sharp_interface)
         return fail(c, LBFD_E_UNSUPPORTED,
                     "sharp-interface mode runs the exact reaction step (no surrogate)");
+    if (c->have_mech && !c->mech.cp.empty())
+        return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: no surrogate");
     const int ns = c->ns, ni = 2 + ns, no = ns, H = MLP_H;
     if (ns < 1 || ni > MLP_KIN || no > MLP_OUT)
         return fail(c, LBFD_E_UNSUPPORTED, "surrogate needs 1..14 species");
@@ -1533,6 +1562,8 @@ lbfd_status lbfd_sample_states(lbfd_ctx* c, const int32_t* cells, int32_t n, flo
     if (!c->have_state) return fail(c, LBFD_E_STATE, "init_state first");
     if (!c->fp32 || c->ns < 1 || 2 + c->ns > MLP_KIN || c->mech.nr < 1)
         return fail(c, LBFD_E_UNSUPPORTED, "sampling needs FP32 mode and a mechanism");
+    if (!c->mech.cp.empty())
+        return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: no surrogate sampling");
     if (n == 0) return LBFD_OK;
     lbfd_status st = set_device(c);
     if (st) return st;

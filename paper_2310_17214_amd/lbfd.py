@@ -81,7 +81,7 @@ class Mechanism(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
                 ("M", _dp), ("dhf", _dp), ("mu_star", _dp), ("nu_f", _ip), ("nu_r", _ip),
                 ("A", _dp), ("beta", _dp), ("theta", _dp), ("reversible", _ip),
-                ("lnKc_a", _dp), ("lnKc_b", _dp)]
+                ("lnKc_a", _dp), ("lnKc_b", _dp), ("cp", _dp)]
 
 
 class Diag(C.Structure):
@@ -211,6 +211,8 @@ class _MechArrays:
                          reversible=i32(m["rev"] if nr else [0], nr),
                          lnKc_a=f64(m["lnKc_a"] if nr else [0], nr),
                          lnKc_b=f64(m["lnKc_b"] if nr else [0], nr))
+        if m.get("cp") is not None:
+            self.arrs["cp"] = f64(m["cp"], ns)
         st = Mechanism()
         st.n_species, st.n_reactions = ns, nr
         for k, a in self.arrs.items():
