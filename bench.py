@@ -244,6 +244,32 @@ def surrogate_measure(wl=None, steps=200, seed=4, log=None, sample_steps=5000, e
         ctx.synchronize()
         by_nsub[k] = e0.elapsed_time(e1) / 50
         del ctx
+    # the stiff reaction schemes on the same bed: every cell's reaction step
+    # in the FP64 island (linearly implicit Euler at one sub-step, adaptive
+    # explicit sub-steps up to 8); T after err_steps against the explicit run
+    stiff = {}
+    for name, scheme, nsub in ((("linearly_implicit", 1, 1), ("adaptive_explicit", 2, 8))
+                               if sweep else ()):
+        s = dict(wl.setup, chem_scheme=scheme, n_sub=nsub)
+        ctx = lbfd.Context(s, wl.phi)
+        ctx.init_state(wl.T0, wl.Y0)
+        ctx.step(10)
+        ctx.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.step(50)
+        e1.record(ctx.stream)
+        ctx.synchronize()
+        ms_s = e0.elapsed_time(e1) / 50
+        ctx.step(err_steps - 60)
+        Ts = ctx.read(lbfd.F_T)
+        stiff[name] = {"chem_scheme": scheme, "n_sub": nsub, "ms_per_step": round(ms_s, 5),
+                       f"max_rel_T_err_vs_explicit_{err_steps}_steps":
+                           float(np.max(np.abs(Ts - ex["T"]) / ex["T"]))}
+        del ctx
+        if log:
+            log(f"{name}: {ms_s:.3f} ms per step")
     ks = sorted(by_nsub)
     even = None
     for a, b in zip(ks, ks[1:]):
@@ -274,6 +300,7 @@ def surrogate_measure(wl=None, steps=200, seed=4, log=None, sample_steps=5000, e
         "heldout_fallback_share": fb_ho,
         "exact_ms_per_step_by_n_sub": {str(k): round(v, 5) for k, v in by_nsub.items()} or None,
         "break_even_n_sub": None if even is None else round(even, 2),
+        "stiff_schemes": stiff or None,
     }
 
 

@@ -609,18 +609,21 @@ def test_diagnostics_follow_the_state_across_island_and_quiet_steps():
 
 
 @pytest.fixture(scope="module")
-def full_bed_oracle():
+def full_bed_oracle(pytestconfig):
     """The FP64 oracle on the full 256x128x128 one-step sphere bed (the
     benchmark's workload, island threshold 1 K): its fields after 100 and
-    after 1000 steps (a few minutes on the host's cores)."""
+    after 1000 steps (a few minutes on the host's cores; a progress line per
+    100 steps reaches the terminal through the capture)."""
+    from conftest import live_line
+
     wl = W.bed_one_step(precision="fp64", steps=0)
-    say(f"oracle: {wl.name}, {O.nthreads()} threads, 100 + 900 steps")
+    live_line(pytestconfig, f"oracle: {wl.name}, {O.nthreads()} threads, 100 + 900 steps")
     orc = O.Oracle(wl.setup, wl.phi)
     orc.init_state(wl.T0, wl.Y0)
     out = []
     for n in range(1, 11):
         orc.step(100)
-        say(f"oracle: {100 * n} steps")
+        live_line(pytestconfig, f"oracle: {100 * n} steps")
         if n in (1, 10):
             out.append(orc.fields())
     return out[0], out[1]
