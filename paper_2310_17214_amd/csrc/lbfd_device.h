@@ -641,6 +641,8 @@ struct StepArgs {
     int stiff;            // stiff reaction scheme (chem_scheme 1 or 2): the FP64 step
                           // and island kernels built with it
     int cpk;              // species heat capacities: the kernels built with them
+    int ext;              // extended boundaries (sharp-interface masks, inlet profile,
+                          // characteristic outlet, Dirichlet faces on periodic axes)
     // FP32 mode: compaction of the cells flagged for the FP64 reaction step
     int* gtot;            // [groups][GSPREAD] flagged cells per group of mask words (added
                           // by the kernels that write the masks, cleared by the island)

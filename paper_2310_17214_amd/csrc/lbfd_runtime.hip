@@ -561,6 +561,22 @@ bool ready_for_tables(const lbfd_ctx* c) { return c->have_params && (c->ns == 0 
 
 // The stability rule for a context with the given params and mechanism, over
 // the temperatures of the initial state when one was set.
+// Extended boundaries of a grid: the characteristic outlet, or an FD
+// Dirichlet face on an LB-periodic axis.
+bool grid_ext(const lbfd_grid& g) {
+    if (g.lb_bc[1] == LBFD_LB_CHARACTERISTIC_OUTLET) return true;
+    for (int f = 0; f < 6; ++f)
+        if (g.lb_bc[f] == LBFD_LB_PERIODIC && g.fd_bc[f] != LBFD_FD_PERIODIC) return true;
+    return false;
+}
+
+// The step runs the kernels of the extended boundaries (sharp-interface
+// masks, inlet profile, characteristic outlet, thermal walls on periodic
+// axes); they exist for up to four species.
+bool uses_ext(const lbfd_ctx* c) {
+    return c->params.sharp_interface || !c->prof.empty() || grid_ext(c->grid);
+}
+
 lbfd_status check_stable(lbfd_ctx* c, const lbfd_params& p, const HostMech* m) {
     if (m && !m->cp.empty()) {  // what the kernels with species heat capacities cover
         if (p.transport_model != 0)
@@ -573,6 +589,10 @@ lbfd_status check_stable(lbfd_ctx* c, const lbfd_params& p, const HostMech* m) {
             return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: at most 9 species");
         if (c->sur)
             return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: no surrogate");
+        if (grid_ext(c->grid) || !c->prof.empty())
+            return fail(c, LBFD_E_UNSUPPORTED,
+                        "species heat capacities: no characteristic outlet, inlet profile or "
+                        "thermal walls on periodic axes");
         if (p.closed)
             for (double v : m->cp)
                 if (!(p.r_gas < v))
@@ -722,6 +742,11 @@ lbfd_status validate_grid(const lbfd_grid* g, std::string& msg) {
         if (lb == LBFD_LB_PERIODIC && fd == LBFD_FD_ZERO_GRADIENT)
             return msg = "an LB-periodic face takes a periodic or Dirichlet FD kind",
                    LBFD_E_INVAL;
+        if (nsm_bucket(g->n_species) > 4 &&
+            (lb == LBFD_LB_CHARACTERISTIC_OUTLET ||
+             (lb == LBFD_LB_PERIODIC && fd != LBFD_FD_PERIODIC)))
+            return msg = "characteristic outlet and thermal walls on periodic axes: at most 4 "
+                         "species", LBFD_E_UNSUPPORTED;
         if (lb == LBFD_LB_VELOCITY_INLET && f != 0)
             return msg = "velocity inlet only on the -x face", LBFD_E_UNSUPPORTED;
         if ((lb == LBFD_LB_PRESSURE_OUTLET || lb == LBFD_LB_CHARACTERISTIC_OUTLET) && f != 1)
@@ -802,6 +827,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.sur = sizeof(R) == 4 && c->sur && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM);
     a.stiff = c->params.chem_scheme != 0;
     a.cpk = c->ns > 0 && !c->mech.cp.empty();
+    a.ext = uses_ext(c);
     a.gtot = dptr<int>(c, c->L.gtot);
     a.list = dptr<int>(c, c->L.list);
     a.count = dptr<int>(c, c->L.count);
@@ -1218,6 +1244,9 @@ lbfd_status lbfd_set_inlet_profile(lbfd_ctx* c, const double* u) {
     }
     if (c->grid.lb_bc[0] != LBFD_LB_VELOCITY_INLET)
         return fail(c, LBFD_E_INVAL, "inlet profile without a velocity inlet on the -x face");
+    if (c->nsm > 4) return fail(c, LBFD_E_UNSUPPORTED, "inlet profile: at most 4 species");
+    if (c->have_mech && !c->mech.cp.empty())
+        return fail(c, LBFD_E_UNSUPPORTED, "species heat capacities: no inlet profile");
     const size_t nr = (size_t)c->grid.ny * c->grid.nz;
     std::vector<double> prof(3 * nr, 0.0);
     for (size_t r = 0; r < nr; ++r) {
