@@ -79,16 +79,39 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_from_profiles(workload_name, bytes_alg):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources (else None)."""
+def _counter_summary(workload_name, bytes_alg):
     path = os.path.join(ROOT, "profiles", f"traffic_{workload_name}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_hash") != kernel_hash() or d.get("bytes_per_launch_alg") != bytes_alg:
         return None
-    return d.get("bytes_per_launch")
+    return d
+
+
+def traffic_from_profiles(workload_name, bytes_alg):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    d = _counter_summary(workload_name, bytes_alg)
+    return None if d is None else d.get("bytes_per_launch")
+
+
+# wave64 VALU instructions the chip can issue per second without packed FP32:
+# 256 CUs x 4 SIMDs, one wave64 instruction every 4 cycles each, at 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4 / 1e9
+
+
+def alu_from_profiles(workload_name, bytes_alg, kernel_ms):
+    """The step kernel against the vector-ALU issue rate: SQ_INSTS_VALU per
+    launch from the committed counter summary (current kernel sources only)
+    over the live mean launch duration."""
+    d = _counter_summary(workload_name, bytes_alg)
+    if d is None or "valu_insts_per_launch" not in d:
+        return None
+    achieved = d["valu_insts_per_launch"] / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "alu", "achieved": round(achieved, 1), "peak": VALU_ISSUE_PEAK,
+            "unit": "G wave64 VALU instructions/s", "frac": round(achieved / VALU_ISSUE_PEAK, 4),
+            "valu_insts_per_launch": d["valu_insts_per_launch"], "summary": d.get("summary")}
 
 
 XGMI_LINK_GBS = 153.0
@@ -400,7 +423,7 @@ def measure(wl, steps, warmup, settle_ms, stream=None, timing=True):
     return out
 
 
-def roofline(wl, m, traffic=None):
+def roofline(wl, m, traffic=None, alu=None):
     """The step kernel against the HBM roofline: achieved = the method's
     algorithmic bytes per cell (survey_bytes_per_cell) x cells / the kernel's
     mean launch duration; the kernel's own count of what it moves beside it."""
@@ -415,7 +438,8 @@ def roofline(wl, m, traffic=None):
             "frac_kernel_bytes": round(kbpc * wl.cells / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "kernel": "step_kernel (fused LB+FD+chemistry+partials)",
             "kernel_ms": round(kms, 5), "kernel_launches": n,
-            "island_ms": round(m["island_kernel"][1], 5), "island_launches": m["island_kernel"][0]}
+            "island_ms": round(m["island_kernel"][1], 5), "island_launches": m["island_kernel"][0],
+            "alu": alu}
 
 
 def config_line(name, steps, warmup, settle_ms, log):
@@ -428,13 +452,16 @@ def config_line(name, steps, warmup, settle_ms, log):
     gen = time.perf_counter() - t0
     log(f"config {wl.name}: {wl.cells} cells (inputs built in {gen:.1f} s)")
     m = measure(wl, steps, warmup, settle_ms)
+    bytes_alg = m["ctx"].bytes_per_cell() * wl.cells
+    traffic = traffic_from_profiles(name, bytes_alg)
+    alu = alu_from_profiles(name, bytes_alg, m["step_kernel"][1])
     line = {"workload": wl.name, "cells": wl.cells,
             "lattice": "D2Q9" if wl.setup["dim"] == 2 else "D3Q19",
             "species": wl.setup["ns"], "reactions": len(wl.setup["mech"]["A"]),
             "precision": wl.setup.get("precision", "fp64"),
             "value": round(m["mlups"], 2), "unit": "MLUPS", "ms_per_step": round(m["ms_step"], 5),
             "steps": steps, "warmup": warmup, "settle_steps": m["settle"],
-            "roofline": roofline(wl, m),
+            "roofline": roofline(wl, m, traffic, alu),
             "diagnostics": {"Tmax": m["diag"]["Tmax"], "umax": m["diag"]["umax"],
                             "n_flagged_fp64": m["diag"]["n_flagged_fp64"],
                             "n_nonfinite": m["diag"]["n_nonfinite"]}}
@@ -490,6 +517,7 @@ def main():
     ctx, diag = m["ctx"], m["diag"]
     bpc = survey_bytes_per_cell(wl.setup)
     traffic = traffic_from_profiles(args.workload, ctx.bytes_per_cell() * wl.cells)
+    alu = alu_from_profiles(args.workload, ctx.bytes_per_cell() * wl.cells, m["step_kernel"][1])
     prec = wl.setup.get("precision", "fp64")
     out = {
         "metric": METRIC,
@@ -509,7 +537,7 @@ def main():
                    "species": wl.setup["ns"], "reactions": len(wl.setup["mech"]["A"]),
                    "precision": prec, "parallelism": "single GPU"},
         "settle_steps": m["settle"],
-        "roofline": roofline(wl, m, traffic),
+        "roofline": roofline(wl, m, traffic, alu),
         "diagnostics": {"mass": diag["mass"], "Tmax": diag["Tmax"], "umax": diag["umax"],
                         "n_flagged_fp64": diag["n_flagged_fp64"],
                         "n_nonfinite": diag["n_nonfinite"]},
