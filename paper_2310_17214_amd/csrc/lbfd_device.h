@@ -637,6 +637,8 @@ struct StepArgs {
     int odd;              // AA parity of this step
     int phase;            // PH_* mask
     int diag;             // write diagnostics partials
+    double* mtpart;       // closed domain: [diagnostics slots] sum of M / T of the new
+                          // state over each slot's cells (null in an open domain)
     int sur;              // FP32 surrogate mode: reactions left to the surrogate kernels
     int stiff;            // stiff reaction scheme (chem_scheme 1 or 2): the FP64 step
                           // and island kernels built with it

@@ -32,7 +32,7 @@ struct HostMech {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, T0, T1, Y0, Y1, divu, phi, part, flags, gtot, list, count, p0, p0part, parf,
+    size_t g, T0, T1, Y0, Y1, divu, phi, part, mtpart, flags, gtot, list, count, p0, p0part, parf,
         pard, scratch, red, sw, sp, solid, smask, inlet, outw, total;
     int nslots;                   // diagnostics slots: step tiles, then island workgroups
     int ngroups;                  // groups of FP64-island mask words
@@ -75,6 +75,7 @@ Layout make_layout(const lbfd_grid& gr) {
     L.phi = take(N * s);
     L.nslots = L.nblocks + ISLAND_WG;
     L.part = take((size_t)L.nslots * DIAG_STRIDE * sizeof(double));
+    L.mtpart = take((size_t)L.nslots * sizeof(double));
     const size_t nwords = (size_t)L.nblocks * (BLOCK / 64);
     L.flags = take(nwords * sizeof(unsigned long long));
     L.ngroups = (int)((nwords + FLAG_GROUP - 1) / FLAG_GROUP);
@@ -134,13 +135,19 @@ __global__ void reduce_partials(const double* __restrict__ part, int nblocks, in
     }
 }
 
-// Closed domain: P0 / P0_in from the partial sums of M / T (mode 0: the initial
-// state, p = 1; mode 1: after a step, p = S0 / S; mode 2: no new sum), then the
-// parameter blocks' EOS numerator and the step's dP0/dt terms for the next step.
-__global__ void p0_update_kernel(const double* __restrict__ part, P0State* __restrict__ st,
-                                 Par<float>* __restrict__ pf, Par<double>* __restrict__ pd,
-                                 int mode) {
-    __shared__ double sh[BLOCK], shc[BLOCK];
+// Closed domain: P0 / P0_in from the sum S of M / T over the cells (mode 0:
+// the initial state, from the P0 sum kernel's (sum, compensation) pairs, p = 1;
+// mode 1: after a step, from the per-slot sums the step's kernels wrote -- the
+// tiles, then the island's workgroups if it listed cells --, p = S0 / S; mode
+// 2: no new sum), then the parameter blocks' EOS numerator and the step's
+// dP0/dt terms for the next step.  The slot sums are combined in a fixed order
+// with compensation (Neumaier), eight loads in flight per thread.
+constexpr int P0_THREADS = 1024;
+__global__ __launch_bounds__(P0_THREADS) void p0_update_kernel(
+    const double* __restrict__ part, const double* __restrict__ mt, int ntile, int nisl,
+    const int* __restrict__ count, P0State* __restrict__ st, Par<float>* __restrict__ pf,
+    Par<double>* __restrict__ pd, int mode) {
+    __shared__ double sh[P0_THREADS], shc[P0_THREADS];
     const int t = threadIdx.x;
     double acc = 0.0, cmp = 0.0;  // compensated, as the partial sums
     auto add = [](double& s, double& c, double x) {
@@ -148,15 +155,28 @@ __global__ void p0_update_kernel(const double* __restrict__ part, P0State* __res
         c += fabs(s) >= fabs(x) ? (s - u) + x : (x - u) + s;
         s = u;
     };
-    if (mode != 2)
-        for (int i = t; i < P0_PARTS; i += BLOCK) {
+    if (mode == 0) {
+        for (int i = t; i < P0_PARTS; i += P0_THREADS) {
             cmp += part[2 * i + 1];
             add(acc, cmp, part[2 * i]);
         }
+    } else if (mode == 1) {
+        const int n = ntile + ((count != nullptr && *count > 0) ? nisl : 0);
+        for (int i0 = t; i0 < n; i0 += 8 * P0_THREADS) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + u * P0_THREADS;
+                v[u] = i < n ? mt[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) add(acc, cmp, v[u]);
+        }
+    }
     sh[t] = acc;
     shc[t] = cmp;
     __syncthreads();
-    for (int o = BLOCK / 2; o > 0; o >>= 1) {
+    for (int o = P0_THREADS / 2; o > 0; o >>= 1) {
         if (t < o) {
             double s = sh[t], c = shc[t] + shc[t + o];
             add(s, c, sh[t + o]);
@@ -605,12 +625,13 @@ lbfd_status check_stable(lbfd_ctx* c, const lbfd_params& p, const HostMech* m) {
     return st ? fail(c, st, msg) : LBFD_OK;
 }
 
-// Closed domain: the sum of M / T over the current state and the P0 update
-// (mode as in p0_update_kernel), on the context's stream.
+// Closed domain: the P0 update (mode as in p0_update_kernel), on the context's
+// stream; the initial state's sum of M / T comes from the P0 sum kernel, a
+// step's from the slots its kernels filled (StepArgs::mt).
 lbfd_status launch_p0(lbfd_ctx* c, int mode) {
     hipError_t e = hipSuccess;
     double* part = dptr<double>(c, c->L.p0part);
-    if (mode != 2) {
+    if (mode == 0) {
         const int N = (int)c->N;
         if (c->fp32)
             e = launch_p0_sum_f32(dptr<float>(c, c->cur ? c->L.T1 : c->L.T0),
@@ -622,9 +643,12 @@ lbfd_status launch_p0(lbfd_ctx* c, int mode) {
                                   dptr<Par<double>>(c, c->L.pard), part, c->stream);
         if (e != hipSuccess) return hip_check(c, e, "P0 sum");
     }
-    hipLaunchKernelGGL(p0_update_kernel, dim3(1), dim3(BLOCK), 0, c->stream, part,
-                       dptr<P0State>(c, c->L.p0), dptr<Par<float>>(c, c->L.parf),
-                       dptr<Par<double>>(c, c->L.pard), mode);
+    // the island's slots take part when the island ran (FP32 with species)
+    const bool island = c->fp32 && c->ns > 0;
+    hipLaunchKernelGGL(p0_update_kernel, dim3(1), dim3(P0_THREADS), 0, c->stream, part,
+                       dptr<double>(c, c->L.mtpart), c->L.nblocks, island ? ISLAND_WG : 0,
+                       island ? dptr<int>(c, c->L.count) : nullptr, dptr<P0State>(c, c->L.p0),
+                       dptr<Par<float>>(c, c->L.parf), dptr<Par<double>>(c, c->L.pard), mode);
     return hip_check(c, hipGetLastError(), "P0 update");
 }
 
@@ -824,6 +848,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.odd = c->odd;
     a.phase = phase;
     a.diag = 1;
+    a.mtpart = c->params.closed ? dptr<double>(c, c->L.mtpart) : nullptr;
     a.sur = sizeof(R) == 4 && c->sur && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM);
     a.stiff = c->params.chem_scheme != 0;
     a.cpk = c->ns > 0 && !c->mech.cp.empty();
