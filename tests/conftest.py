@@ -11,13 +11,12 @@ def pytest_configure(config):
 
 
 def live_line(config, msg):
-    """Write a progress line to the terminal even while pytest captures the
-    test's output (long tests keep the run's output moving)."""
-    tr = config.pluginmanager.get_plugin("terminalreporter")
-    if tr is None:
+    """Write a progress line to the run's output even while pytest captures
+    the test's output (long tests keep the run's output moving): the capture
+    is suspended for the write."""
+    capman = config.pluginmanager.getplugin("capturemanager")
+    if capman is None:
         print(msg, flush=True)
         return
-    tr.write_line(str(msg))
-    tw = getattr(tr, "_tw", None)
-    if tw is not None and hasattr(tw, "flush"):
-        tw.flush()
+    with capman.global_and_fixture_disabled():
+        print(msg, flush=True)
