@@ -18,6 +18,7 @@ constexpr int DIAG_STRIDE = 32;  // doubles of partials per workgroup
 constexpr int FLAG_GROUP = 4 * BLOCK;  // FP64-island mask words per scan group
 constexpr int GSPREAD = 16;            // counters per group (word w adds to counter w % GSPREAD)
 constexpr int ISLAND_WG = 1024;        // workgroups (and diagnostics slots) of the island
+constexpr int MLP_SLOT_WG = 1024;      // most surrogate workgroups (two diagnostics slots each)
 enum {
     DG_MASS = 0, DG_SP = 1, DG_ENTH = 17, DG_KIN = 18, DG_UMAX = 19, DG_TMIN = 20,
     DG_TMAX = 21, DG_NONFIN = 22, DG_TAUBAD = 23, DG_NEGY = 24, DG_FLAG = 25, DG_FALLBACK = 26,

@@ -34,7 +34,8 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 struct Layout {
     size_t g, T0, T1, Y0, Y1, divu, phi, part, mtpart, flags, gtot, list, count, p0, p0part, parf,
         pard, scratch, red, sw, sp, solid, smask, inlet, outw, total;
-    int nslots;                   // diagnostics slots: step tiles, then island workgroups
+    int nslots;                   // diagnostics slots: step tiles, island workgroups, then
+                                  // two per surrogate workgroup
     int ngroups;                  // groups of FP64-island mask words
     int nbx, nby, zc, nblocks, grid;  // step kernel: 64 x TH tiles of one plane,
                                       // grid padded to a multiple of the 8 XCDs
@@ -73,7 +74,9 @@ Layout make_layout(const lbfd_grid& gr) {
     L.Y1 = take((size_t)nsm_bucket(gr.n_species) * N * s);
     L.divu = take(N * s);
     L.phi = take(N * s);
-    L.nslots = L.nblocks + ISLAND_WG;
+    // the surrogate's slots exist where it can run (FP32 with species)
+    const bool sur = gr.precision == LBFD_FP32 && gr.n_species > 0;
+    L.nslots = L.nblocks + ISLAND_WG + (sur ? 2 * MLP_SLOT_WG : 0);
     L.part = take((size_t)L.nslots * DIAG_STRIDE * sizeof(double));
     L.mtpart = take((size_t)L.nslots * sizeof(double));
     const size_t nwords = (size_t)L.nblocks * (BLOCK / 64);
@@ -100,13 +103,16 @@ Layout make_layout(const lbfd_grid& gr) {
     return L;
 }
 
-// Fixed-order reduction of the partial slots.  Slots from isl0 on belong to
-// the FP64 island: their sums and extrema describe the last step only if it
-// listed cells (*count > 0); their counters always accumulate.
-__global__ void reduce_partials(const double* __restrict__ part, int nblocks, int ns,
-                                double* __restrict__ out, int isl0,
-                                const int* __restrict__ count) {
+// Fixed-order reduction of the partial slots: ntile step tiles, then nisl
+// island workgroups, then nmlp surrogate slots.  The island's sums and extrema
+// describe the last step only if it listed cells (*count > 0), the
+// surrogate's only if the last step ran it (mlp_live); counters always
+// accumulate.
+__global__ void reduce_partials(const double* __restrict__ part, int ntile, int nisl, int nmlp,
+                                int ns, double* __restrict__ out,
+                                const int* __restrict__ count, int mlp_live) {
     const bool island_live = count != nullptr && *count > 0;
+    const int nblocks = ntile + nisl + nmlp;
     __shared__ double sh[BLOCK];
     const int t = threadIdx.x;
     for (int s = 0; s < DG_COUNT; ++s) {
@@ -116,8 +122,9 @@ __global__ void reduce_partials(const double* __restrict__ part, int nblocks, in
         }
         const bool mx = s == DG_UMAX || s == DG_TMAX, mn = s == DG_TMIN;
         double acc = mx ? -1e300 : mn ? 1e300 : 0.0;
-        const int nb = (s < DG_NONFIN && !island_live) ? min(nblocks, isl0) : nblocks;
-        for (int b = t; b < nb; b += BLOCK) {
+        const bool cnt = s >= DG_NONFIN;
+        for (int b = t; b < nblocks; b += BLOCK) {
+            if (!(b < ntile || cnt || (b < ntile + nisl ? island_live : mlp_live != 0))) continue;
             const double v = part[(size_t)b * DIAG_STRIDE + s];
             acc = mx ? fmax(acc, v) : mn ? fmin(acc, v) : acc + v;
         }
@@ -138,15 +145,16 @@ __global__ void reduce_partials(const double* __restrict__ part, int nblocks, in
 // Closed domain: P0 / P0_in from the sum S of M / T over the cells (mode 0:
 // the initial state, from the P0 sum kernel's (sum, compensation) pairs, p = 1;
 // mode 1: after a step, from the per-slot sums the step's kernels wrote -- the
-// tiles, then the island's workgroups if it listed cells --, p = S0 / S; mode
+// tiles, the island's workgroups if it listed cells, the surrogate's slots if
+// the step ran it --, p = S0 / S; mode
 // 2: no new sum), then the parameter blocks' EOS numerator and the step's
 // dP0/dt terms for the next step.  The slot sums are combined in a fixed order
 // with compensation (Neumaier), eight loads in flight per thread.
 constexpr int P0_THREADS = 1024;
 __global__ __launch_bounds__(P0_THREADS) void p0_update_kernel(
     const double* __restrict__ part, const double* __restrict__ mt, int ntile, int nisl,
-    const int* __restrict__ count, P0State* __restrict__ st, Par<float>* __restrict__ pf,
-    Par<double>* __restrict__ pd, int mode) {
+    int nmlp, const int* __restrict__ count, int mlp_live, P0State* __restrict__ st,
+    Par<float>* __restrict__ pf, Par<double>* __restrict__ pd, int mode) {
     __shared__ double sh[P0_THREADS], shc[P0_THREADS];
     const int t = threadIdx.x;
     double acc = 0.0, cmp = 0.0;  // compensated, as the partial sums
@@ -161,13 +169,15 @@ __global__ __launch_bounds__(P0_THREADS) void p0_update_kernel(
             add(acc, cmp, part[2 * i]);
         }
     } else if (mode == 1) {
-        const int n = ntile + ((count != nullptr && *count > 0) ? nisl : 0);
+        const bool island_live = count != nullptr && *count > 0;
+        const int n = ntile + nisl + nmlp;
         for (int i0 = t; i0 < n; i0 += 8 * P0_THREADS) {
             double v[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int i = i0 + u * P0_THREADS;
-                v[u] = i < n ? mt[i] : 0.0;
+                const bool use = i < ntile || (i < ntile + nisl ? island_live : mlp_live != 0);
+                v[u] = i < n && use ? mt[i] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) add(acc, cmp, v[u]);
@@ -223,6 +233,8 @@ struct lbfd_ctx {
     HostMech mech;
     bool have_phi = false, have_params = false, have_mech = false, have_state = false;
     int cur = 0, odd = 0;
+    bool last_sur = false;  // the last step ran the surrogate (its diagnostics slots are live)
+    int mlp_grid = 0;       // surrogate workgroups (two diagnostics slots each)
     double state_T[2] = {0.0, 0.0};  // min and max T of the initial state
     double T_ref = 0.0;  // the temperature planes hold T - T_ref (FP32: T_solid at init_state)
     int64_t steps = 0;
@@ -643,11 +655,12 @@ lbfd_status launch_p0(lbfd_ctx* c, int mode) {
                                   dptr<Par<double>>(c, c->L.pard), part, c->stream);
         if (e != hipSuccess) return hip_check(c, e, "P0 sum");
     }
-    // the island's slots take part when the island ran (FP32 with species)
+    // the island's and the surrogate's slots exist in FP32 mode with species
     const bool island = c->fp32 && c->ns > 0;
     hipLaunchKernelGGL(p0_update_kernel, dim3(1), dim3(P0_THREADS), 0, c->stream, part,
                        dptr<double>(c, c->L.mtpart), c->L.nblocks, island ? ISLAND_WG : 0,
-                       island ? dptr<int>(c, c->L.count) : nullptr, dptr<P0State>(c, c->L.p0),
+                       island ? 2 * c->mlp_grid : 0, island ? dptr<int>(c, c->L.count) : nullptr,
+                       c->last_sur ? 1 : 0, dptr<P0State>(c, c->L.p0),
                        dptr<Par<float>>(c, c->L.parf), dptr<Par<double>>(c, c->L.pard), mode);
     return hip_check(c, hipGetLastError(), "P0 update");
 }
@@ -878,7 +891,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
             if (e == hipSuccess)
                 e = launch_mlp_step_f32(c->dim, c->nsm, a, dptr<SurWeights>(c, c->L.sw),
                                         dptr<SurPar>(c, c->L.sp),
-                                        std::min(c->n_cu, (c->L.nblocks + 1) / 2), c->stream);
+                                        c->mlp_grid, c->stream);
             if (e == hipSuccess) e = time_mark(c, LBFD_KERNEL_SURROGATE, true);
         }
         // every FP32 step with species runs the island (an empty list when no
@@ -889,6 +902,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
             if (e == hipSuccess) e = time_mark(c, LBFD_KERNEL_ISLAND, true);
         }
     }
+    c->last_sur = a.sur != 0;
     return hip_check(c, e, "step kernel launch");
 }
 
@@ -1007,6 +1021,7 @@ lbfd_status lbfd_create(const lbfd_grid* grid, void* dev_workspace, size_t bytes
         delete c;
         return LBFD_E_DEVICE;
     }
+    c->mlp_grid = std::max(1, std::min({c->n_cu, (c->L.nblocks + 1) / 2, MLP_SLOT_WG}));
     *out = c;
     return LBFD_OK;
 }
@@ -1181,6 +1196,7 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
                                      (size_t)c->L.nslots * DIAG_STRIDE * sizeof(double), c->stream),
                    "clear diagnostics");
     if (st) return st;
+    c->last_sur = false;
     st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.count), 0, sizeof(int), c->stream),
                    "clear island count");
     if (st) return st;
@@ -1430,8 +1446,10 @@ lbfd_status lbfd_diagnostics(lbfd_ctx* c, lbfd_diag* out) {
     double* red = dptr<double>(c, c->L.red);
     const bool island = c->fp32 && c->ns > 0;
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(BLOCK), 0, c->stream,
-                       dptr<double>(c, c->L.part), island ? c->L.nslots : c->L.nblocks, c->ns,
-                       red, c->L.nblocks, island ? dptr<int>(c, c->L.count) : (const int*)nullptr);
+                       dptr<double>(c, c->L.part), c->L.nblocks, island ? ISLAND_WG : 0,
+                       island ? 2 * c->mlp_grid : 0, c->ns, red,
+                       island ? dptr<int>(c, c->L.count) : (const int*)nullptr,
+                       c->last_sur ? 1 : 0);
     if ((st = hip_check(c, hipGetLastError(), "diagnostics launch"))) return st;
     double h[DG_COUNT];
     st = hip_check(c, hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, c->stream),
