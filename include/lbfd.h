@@ -270,7 +270,10 @@ typedef struct {
                             rate or property                                      */
 } lbfd_stability_report;
 
-/* Evaluate the rule for a grid, params and mechanism (mech may be NULL: no
+/* The explicit steps of Sec. 3.3 (forward Euler FD update, n_sub explicit
+ * reaction sub-steps) and the BGK relaxation of Sec. 3.3 are stable under
+ * the bounds of this rule.
+ * Evaluate the rule for a grid, params and mechanism (mech may be NULL: no
  * reaction bound, and a Wilke closure then needs it and is skipped) over the
  * temperatures T_in, T_solid, the Dirichlet faces, params->T_max and the
  * extra range [T_lo, T_hi] (pass 0, 0 for none).  Fills *out (may be NULL);
@@ -349,7 +352,8 @@ lbfd_status lbfd_set_populations(lbfd_ctx* ctx, const double* g, const double* d
  * or for |u| > 0.1 (the low-Mach limit). */
 lbfd_status lbfd_set_inlet_profile(lbfd_ctx* ctx, const double* u);
 
-/* Characteristic outlet: overwrite the incoming wave amplitude w of every
+/* Characteristic (non-reflecting) outlet of Sec. 4.1, after Poinsot and
+ * Lele: overwrite the incoming wave amplitude w of every
  * outlet row (ny*nz doubles, z*ny + y, host memory) -- with lbfd_init_state
  * and lbfd_set_populations this restores a checkpoint.  LBFD_E_INVAL for
  * non-finite values or a grid without that outlet; LBFD_E_STATE before
@@ -371,7 +375,9 @@ lbfd_status lbfd_set_p0_state(lbfd_ctx* ctx, const double* in);
  * returns without waiting.  LBFD_E_STATE before lbfd_init_state. */
 lbfd_status lbfd_step(lbfd_ctx* ctx, int32_t n);
 
-/* Enqueue n steps running only the phases in phase_mask (test hook).  Without
+/* Enqueue n steps running only the phases in phase_mask (test hook): LB
+ * (Sec. 3.3, the populations and the coupling force of Sec. 3.2.1), FD (the
+ * transport of T and Y_k, Sec. 3.3) and CHEM (the sources of Eqs. 8 and 9).  Without
  * LB the velocity is zero and populations are untouched; without FD, T and Y
  * enter the reaction step unchanged; without CHEM no reaction is applied. */
 lbfd_status lbfd_step_phase(lbfd_ctx* ctx, int32_t n, int32_t phase_mask);
@@ -390,7 +396,7 @@ lbfd_status lbfd_read(lbfd_ctx* ctx, int32_t field, int32_t component, double* h
  * 0, with *out filled. */
 lbfd_status lbfd_diagnostics(lbfd_ctx* ctx, lbfd_diag* out);
 
-/* Wait for the context's stream. */
+/* Wait for the context's stream (host synchronisation; no passage). */
 lbfd_status lbfd_synchronize(lbfd_ctx* ctx);
 
 /* Algorithmic HBM bytes one cell moves in one lbfd_step on this grid: each
