@@ -367,7 +367,7 @@ def copy_probe():
                       b.numel() * 4}))
 
 
-def survey_bytes_per_cell(setup):
+def method_bytes_per_cell(setup):
     """Algorithmic bytes per cell and step of the method, each array moved
     once: the LB part reads and writes the Q populations in place and reads
     rho, T, phi_s and divu and writes u; the FD + chemistry part reads T, Y_k,
@@ -425,9 +425,9 @@ def measure(wl, steps, warmup, settle_ms, stream=None, timing=True):
 
 def roofline(wl, m, traffic=None, alu=None):
     """The step kernel against the HBM roofline: achieved = the method's
-    algorithmic bytes per cell (survey_bytes_per_cell) x cells / the kernel's
+    algorithmic bytes per cell (method_bytes_per_cell) x cells / the kernel's
     mean launch duration; the kernel's own count of what it moves beside it."""
-    bpc = survey_bytes_per_cell(wl.setup)
+    bpc = method_bytes_per_cell(wl.setup)
     kbpc = m["ctx"].bytes_per_cell()
     n, kms = m["step_kernel"]
     achieved = bpc * wl.cells / (kms * 1e-3) / 1e9
@@ -515,7 +515,7 @@ def main():
     stream = torch.cuda.current_stream()
     m = measure(wl, args.steps, args.warmup, args.settle_ms, stream=stream)
     ctx, diag = m["ctx"], m["diag"]
-    bpc = survey_bytes_per_cell(wl.setup)
+    bpc = method_bytes_per_cell(wl.setup)
     traffic = traffic_from_profiles(args.workload, ctx.bytes_per_cell() * wl.cells)
     alu = alu_from_profiles(args.workload, ctx.bytes_per_cell() * wl.cells, m["step_kernel"][1])
     prec = wl.setup.get("precision", "fp64")
