@@ -15,8 +15,8 @@ constexpr int MAXR = 32;
 constexpr int MAXR_TAB = MAXR + 2;  // reaction table entries: two segments, each padded to pairs
 constexpr int BLOCK = 256;       // threads per workgroup: 4 wave64
 constexpr int DIAG_STRIDE = 32;  // doubles of partials per workgroup
-constexpr int FLAG_CNT = 64;    // counters of flagged cells (word w adds to counter w % FLAG_CNT)
-constexpr int ISLAND_CH = 64;   // mask words an island workgroup lists at a time
+constexpr int FLAG_GROUP = 4 * BLOCK;  // FP64-island mask words per scan group
+constexpr int GSPREAD = 16;            // counters per group (word w adds to counter w % GSPREAD)
 constexpr int ISLAND_WG = 1024;        // workgroups (and diagnostics slots) of the island
 constexpr int MLP_SLOT_WG = 1024;      // most surrogate workgroups (two diagnostics slots each)
 enum {
@@ -647,10 +647,10 @@ struct StepArgs {
     int ext;              // extended boundaries (sharp-interface masks, inlet profile,
                           // characteristic outlet, Dirichlet faces on periodic axes)
     // FP32 mode: compaction of the cells flagged for the FP64 reaction step
-    int* gtot;            // [FLAG_CNT] flagged cells of this step (added by the kernels
-                          // that write the masks)
-    int* gtot_next;       // [FLAG_CNT] the next step's counters, cleared by the island
-    int* count;           // [1] number of flagged cells of the last step
+    int* gtot;            // [groups][GSPREAD] flagged cells per group of mask words (added
+                          // by the kernels that write the masks, cleared by the island)
+    int* list;            // [N] flagged cell indices in mask order
+    int* count;           // [1] number of listed cells
     int P_nx, P_ny;       // grid extents (for the list kernel)
     // base of every plane, filled per launch: separate kernel arguments keep
     // each plane's base in scalar registers, so an access costs one shared

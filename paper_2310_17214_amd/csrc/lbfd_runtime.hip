@@ -32,10 +32,11 @@ struct HostMech {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t g, T0, T1, Y0, Y1, divu, phi, part, mtpart, flags, gtot, count, p0, p0part, parf,
+    size_t g, T0, T1, Y0, Y1, divu, phi, part, mtpart, flags, gtot, list, count, p0, p0part, parf,
         pard, scratch, red, sw, sp, solid, smask, inlet, outw, total;
     int nslots;                   // diagnostics slots: step tiles, island workgroups, then
                                   // two per surrogate workgroup
+    int ngroups;                  // groups of FP64-island mask words
     int nbx, nby, zc, nblocks, grid;  // step kernel: 64 x TH tiles of one plane,
                                       // grid padded to a multiple of the 8 XCDs
     int nlin;                     // one-cell-per-thread kernels
@@ -80,7 +81,9 @@ Layout make_layout(const lbfd_grid& gr) {
     L.mtpart = take((size_t)L.nslots * sizeof(double));
     const size_t nwords = (size_t)L.nblocks * (BLOCK / 64);
     L.flags = take(nwords * sizeof(unsigned long long));
-    L.gtot = take(2 * FLAG_CNT * sizeof(int));  // two halves, alternating by step
+    L.ngroups = (int)((nwords + FLAG_GROUP - 1) / FLAG_GROUP);
+    L.gtot = take((size_t)L.ngroups * GSPREAD * sizeof(int));
+    L.list = take(N * sizeof(int));
     L.count = take(sizeof(int));
     L.p0 = take(sizeof(P0State));
     L.p0part = take(2 * P0_PARTS * sizeof(double));
@@ -231,7 +234,6 @@ struct lbfd_ctx {
     bool have_phi = false, have_params = false, have_mech = false, have_state = false;
     int cur = 0, odd = 0;
     bool last_sur = false;  // the last step ran the surrogate (its diagnostics slots are live)
-    int gpar = 0;           // half of the flagged-cell counters the next step adds to
     int mlp_grid = 0;       // surrogate workgroups (two diagnostics slots each)
     double state_T[2] = {0.0, 0.0};  // min and max T of the initial state
     double T_ref = 0.0;  // the temperature planes hold T - T_ref (FP32: T_solid at init_state)
@@ -864,8 +866,8 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.stiff = c->params.chem_scheme != 0;
     a.cpk = c->ns > 0 && !c->mech.cp.empty();
     a.ext = uses_ext(c);
-    a.gtot = dptr<int>(c, c->L.gtot) + c->gpar * FLAG_CNT;
-    a.gtot_next = dptr<int>(c, c->L.gtot) + (1 - c->gpar) * FLAG_CNT;
+    a.gtot = dptr<int>(c, c->L.gtot);
+    a.list = dptr<int>(c, c->L.list);
     a.count = dptr<int>(c, c->L.count);
     a.P_nx = c->grid.nx;
     a.P_ny = c->grid.ny;
@@ -901,7 +903,6 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
         }
     }
     c->last_sur = a.sur != 0;
-    if (sizeof(R) == 4 && c->ns > 0) c->gpar ^= 1;  // the island cleared the other half
     return hip_check(c, e, "step kernel launch");
 }
 
@@ -1200,7 +1201,7 @@ lbfd_status lbfd_init_state(lbfd_ctx* c, const double* T, const double* Y, const
                    "clear island count");
     if (st) return st;
     st = hip_check(c, hipMemsetAsync(dptr<char>(c, c->L.gtot), 0,
-                                     2 * FLAG_CNT * sizeof(int), c->stream),
+                                     (size_t)c->L.ngroups * GSPREAD * sizeof(int), c->stream),
                    "clear island group counts");
     if (st) return st;
     // characteristic outlet: the incoming wave amplitude starts at zero
