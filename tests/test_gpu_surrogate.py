@@ -251,3 +251,76 @@ def test_s3_trained_surrogate_tracks_the_exact_path_within_one_percent():
         f"{d['n_fallback']}; Tmax exact {Te.max():.1f} surrogate {Ts.max():.1f}")
     assert err.max() <= 1e-2
     assert d["n_nonfinite"] == 0
+
+
+def _zero_source_surrogate(ns, T_hi):
+    """A surrogate that predicts a zero source for every input with T <= T_hi
+    (zero output layer, zero output mean): every such cell passes the checks
+    and is finished by the surrogate kernel, the others fall back."""
+    T, Y = _random_states(400, ns, 4)
+    w, norm = _model(ns, T, Y, 13)
+    w["W3"][:] = 0.0
+    w["b3"][:] = 0.0
+    norm = dict(norm, mu_y=np.zeros(ns), sd_y=np.ones(ns),
+                lo=np.array([0.0, 1.0] + [0.0] * ns), hi=np.array([T_hi, 1.0] + [1.0] * ns))
+    return w, norm
+
+
+@pytest.mark.parametrize("T_hi", [1e5, 800.0])
+def test_surrogate_step_diagnostics_equal_the_sums_of_the_fields(T_hi):
+    """The state sums of a surrogate step come from the surrogate kernel's own
+    slots (and the island's for the cells that fall back): mass, species mass
+    and the T extrema equal the sums and extrema of the read-back fields."""
+    wl = _crop9()
+    ns = wl.setup["ns"]
+    w, norm = _zero_source_surrogate(ns, T_hi)
+    say(f"surrogate-step diagnostics, T_hi {T_hi}, 4 steps")
+    ctx = lb().Context(wl.setup, wl.phi)
+    _install(ctx, w, norm)
+    ctx.init_state(wl.T0, wl.Y0)
+    ctx.step(4)
+    d, f = ctx.diagnostics(), ctx.fields()
+    N = ctx.N
+    if T_hi > 1e4:
+        assert d["n_fallback"] == 0
+    else:
+        assert 0 < d["n_fallback"] < 4 * N
+    rho = f["rho"].astype(np.float64)
+    # the kernels sum the FP32 EOS of the stored state, the read the FP64 one
+    assert d["mass"] == pytest.approx(rho.sum(), rel=1e-6)
+    for k in range(ns):
+        assert d["species_mass"][k] == pytest.approx((rho * f["Y"][k]).sum(), rel=1e-6,
+                                                     abs=1e-9 * rho.sum())
+    assert d["Tmin"] == f["T"].min() and d["Tmax"] == f["T"].max()
+
+
+def test_surrogate_step_p0_equals_the_ratio_of_the_field_sums():
+    """Closed domain with every cell finished by the surrogate kernel: P0 /
+    P0_in = S0 / S with S the sum of M / T over the cells (Sec. 3.1), the sums
+    recomputed from the read-back initial and final fields."""
+    wl = _crop9()
+    s = dict(wl.setup)
+    s["lb_bc"] = ["wall" if b in ("inlet", "outlet") else b for b in s["lb_bc"]]
+    s["u_in"] = [0.0, 0.0, 0.0]
+    s["closed"], s["r_gas"] = 1, 0.3 * s["cp"]
+    ns = s["ns"]
+    # the FP32 parameter block's 1 / M_k, as the kernels read it
+    inv_m = (1.0 / np.asarray(s["mech"]["M"], np.float64)).astype(np.float32).astype(np.float64)
+    w, norm = _zero_source_surrogate(ns, 1e5)
+
+    def sum_m_over_t(f):
+        im = np.tensordot(inv_m, f["Y"].astype(np.float64), axes=1)
+        return float(np.sum(1.0 / (im * f["T"])))
+
+    say("surrogate-step P0, closed domain, 5 steps")
+    ctx = lb().Context(s, wl.phi)
+    _install(ctx, w, norm)
+    ctx.init_state(wl.T0, wl.Y0)
+    s0 = sum_m_over_t(ctx.fields())
+    ctx.step(5)
+    d, f = ctx.diagnostics(), ctx.fields()
+    assert d["n_fallback"] == 0
+    p = s0 / sum_m_over_t(f)
+    say(d["p0_ratio"], p)
+    assert d["p0_ratio"] != 1.0
+    assert d["p0_ratio"] == pytest.approx(p, rel=1e-12)
