@@ -420,13 +420,17 @@ __device__ __forceinline__ void rates_jacobian(const Par<double>& P, double T, c
                                                double rho, double* f,
                                                double (&J)[NSM + 1][NSM + 1]) {
     constexpr int N1 = NSM + 1;
-    double X[NSM + 1], w[NSM], GT[NSM], G[NSM][NSM];
+    // The sums over the reactions accumulate in the output arrays: f[k]
+    // takes sum_j s_kj Q_j, J[k][m] sum_j s_kj dQ_j/d[X_m] and J[k][NSM]
+    // sum_j s_kj dQ_j/dT, each scaled in place afterwards (one matrix in
+    // registers instead of two).
+    double X[NSM + 1];
 #pragma unroll
     for (int k = 0; k < NSM; ++k) {
         X[k] = rho * Y[k] * P.invM[k];
-        w[k] = GT[k] = 0.0;
+        f[k] = 0.0;
 #pragma unroll
-        for (int m = 0; m < NSM; ++m) G[k][m] = 0.0;
+        for (int m = 0; m < N1; ++m) J[k][m] = 0.0;
     }
     X[NSM] = 1.0;
     const double invT = 1.0 / T;
@@ -479,21 +483,21 @@ __device__ __forceinline__ void rates_jacobian(const Par<double>& P, double T, c
 #pragma unroll
         for (int k = 0; k < NSM; ++k) {
             const double s = r.nud[j][k];
-            w[k] += s * Qj;
-            GT[k] += s * dQT;
+            f[k] += s * Qj;
+            J[k][NSM] += s * dQT;
 #pragma unroll
-            for (int m = 0; m < NSM; ++m) G[k][m] += s * dQ[m];
+            for (int m = 0; m < NSM; ++m) J[k][m] += s * dQ[m];
         }
     }
     const double irho = 1.0 / rho;
     double fT = 0.0;
 #pragma unroll
     for (int k = 0; k < NSM; ++k) {
-        f[k] = P.M[k] * w[k] * irho;
+        f[k] = P.M[k] * f[k] * irho;
         fT -= P.dhf[k] * f[k] * P.inv_cp;
 #pragma unroll
-        for (int m = 0; m < NSM; ++m) J[k][m] = P.M[k] * P.invM[m] * G[k][m];
-        J[k][NSM] = P.M[k] * irho * GT[k];
+        for (int m = 0; m < NSM; ++m) J[k][m] = P.M[k] * P.invM[m] * J[k][m];
+        J[k][NSM] = P.M[k] * irho * J[k][NSM];
     }
     f[NSM] = fT;
 #pragma unroll
@@ -503,6 +507,77 @@ __device__ __forceinline__ void rates_jacobian(const Par<double>& P, double T, c
         for (int k = 0; k < NSM; ++k) v -= P.dhf[k] * J[k][m];
         J[NSM][m] = v * P.inv_cp;
     }
+}
+
+// The diagonal of the same Jacobian, d[i] = J[i][i], by the same arithmetic
+// element for element (the adaptive scheme needs only its largest
+// magnitude, and the full matrix would hold about 200 registers).
+template <int NSM>
+__device__ __forceinline__ void rates_jacobian_diag(const Par<double>& P, double T,
+                                                    const double* Y, double rho, double* d) {
+    double X[NSM + 1], G[NSM], GT[NSM];
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) {
+        X[k] = rho * Y[k] * P.invM[k];
+        G[k] = GT[k] = 0.0;
+    }
+    X[NSM] = 1.0;
+    const double invT = 1.0 / T;
+    const double lgT = P.any_beta ? flog(T) : 0.0;
+    const Rxn<double>& r = P.rx;
+    for (int j = 0; j < P.n_tab; ++j) {
+        const int nf = j < P.n_lo ? 2 : 4;
+        const double kf = r.A[j] * fexp(r.beta[j] * lgT - r.theta[j] * invT);
+        const double dlf = (r.beta[j] + r.theta[j] * invT) * invT;
+        const bool rv = r.rev[j] != 0;
+        const double kr = rv ? kf * fexp(-(r.lnKc_a[j] + r.lnKc_b[j] * invT)) : 0.0;
+        const double dlr = dlf + r.lnKc_b[j] * invT * invT;
+        int fi[4], ri[4];
+        double xf[4], xr[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            fi[q] = q < nf ? (int)((r.fidx[j] >> (8 * q)) & 255u) : NSM;
+            ri[q] = q < nf ? (int)((r.ridx[j] >> (8 * q)) & 255u) : NSM;
+            xf[q] = X[fi[q]];
+            xr[q] = X[ri[q]];
+        }
+        const double qf = kf * xf[0] * xf[1] * xf[2] * xf[3];
+        const double qr = kr * xr[0] * xr[1] * xr[2] * xr[3];
+        double df[4], dr[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double a = kf, b = kr;
+#pragma unroll
+            for (int o = 0; o < 4; ++o)
+                if (o != q) {
+                    a *= xf[o];
+                    b *= xr[o];
+                }
+            df[q] = a;
+            dr[q] = b;
+        }
+        const double dQT = qf * dlf - qr * dlr;
+#pragma unroll
+        for (int k = 0; k < NSM; ++k) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v += fi[q] == k ? df[q] : 0.0;
+                v -= ri[q] == k ? dr[q] : 0.0;
+            }
+            const double s = r.nud[j][k];
+            GT[k] += s * dQT;
+            G[k] += s * v;
+        }
+    }
+    const double irho = 1.0 / rho;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < NSM; ++k) {
+        d[k] = P.M[k] * P.invM[k] * G[k];
+        v -= P.dhf[k] * (P.M[k] * irho * GT[k]);
+    }
+    d[NSM] = v * P.inv_cp;
 }
 
 // A x = b by Gaussian elimination with partial pivoting, b overwritten with
@@ -558,11 +633,14 @@ __device__ __forceinline__ void solve_pivoted(double (&A)[n][n], double (&b)[n])
 //      (I - h J) dy = h f at the sub-step's state and density, y += dy;
 //   2: n = min(n_sub, max(1, ceil(2 kappa))) explicit sub-steps of length
 //      1/n, kappa = max_i |J_ii| at the cell's state.
-template <int NSM>
+// CS: the scheme fixed at compile time (1 or 2: a kernel carries only that
+// scheme's registers), or -1 to take it from the parameters.
+template <int NSM, int CS = -1>
 __device__ __forceinline__ void chem_step(const Par<double>& P, double& T, double* Y) {
     if constexpr (NSM > 0 && NSM <= 9) {
         constexpr int N1 = NSM + 1;
-        if (P.chem_scheme == 1) {
+        const int cs = CS >= 0 ? CS : P.chem_scheme;
+        if (cs == 1) {
             const double h = P.h_sub;
             for (int it = 0; it < P.n_sub; ++it) {
                 double J[N1][N1], b[N1];
@@ -581,11 +659,11 @@ __device__ __forceinline__ void chem_step(const Par<double>& P, double& T, doubl
             }
             return;
         }
-        if (P.chem_scheme == 2) {
-            double J[N1][N1], f[N1], kap = 0.0;
-            rates_jacobian<NSM>(P, T, Y, eos<double, NSM>(P, T, Y), f, J);
+        if (cs == 2) {
+            double d[N1], kap = 0.0;
+            rates_jacobian_diag<NSM>(P, T, Y, eos<double, NSM>(P, T, Y), d);
 #pragma unroll
-            for (int i = 0; i < N1; ++i) kap = fmax(kap, fabs(J[i][i]));
+            for (int i = 0; i < N1; ++i) kap = fmax(kap, fabs(d[i]));
             const double m = ceil(2.0 * kap);
             const int nsub = m < 1.0 ? 1 : m > (double)P.n_sub ? P.n_sub : (int)m;
             const double h = 1.0 / nsub;
@@ -641,7 +719,7 @@ struct StepArgs {
     double* mtpart;       // closed domain: [diagnostics slots] sum of M / T of the new
                           // state over each slot's cells (null in an open domain)
     int sur;              // FP32 surrogate mode: reactions left to the surrogate kernels
-    int stiff;            // stiff reaction scheme (chem_scheme 1 or 2): the FP64 step
+    int stiff;            // stiff reaction scheme (chem_scheme 1 or 2, 0 none): the FP64 step
                           // and island kernels built with it
     int cpk;              // species heat capacities: the kernels built with them
     int ext;              // extended boundaries (sharp-interface masks, inlet profile,

@@ -863,7 +863,7 @@ lbfd_status launch_step(lbfd_ctx* c, int phase) {
     a.diag = 1;
     a.mtpart = c->params.closed ? dptr<double>(c, c->L.mtpart) : nullptr;
     a.sur = sizeof(R) == 4 && c->sur && c->ns > 0 && c->mech.nr > 0 && (phase & PH_CHEM);
-    a.stiff = c->params.chem_scheme != 0;
+    a.stiff = c->params.chem_scheme;  // 0 none, 1 or 2
     a.cpk = c->ns > 0 && !c->mech.cp.empty();
     a.ext = uses_ext(c);
     a.gtot = dptr<int>(c, c->L.gtot);

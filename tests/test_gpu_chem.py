@@ -125,10 +125,13 @@ def test_one_step_crop_fp32_1000_steps(scheme, n_sub):
     assert d["n_flagged_fp64"] >= 1000 * wl32.cells  # every cell, every step
 
 
-def test_nine_species_crop_fp32_linearly_implicit_1000_steps():
-    wl32 = _crop9("fp32", 1, 1)
-    wl64 = _crop9("fp64", 1, 1)
-    say("nine-species crop fp32 linearly implicit, 1000 steps")
+@pytest.mark.parametrize("scheme,n_sub", [(1, 1), (2, 16)])
+def test_nine_species_crop_fp32_1000_steps(scheme, n_sub):
+    """Both stiff schemes in the FP64 island (a kernel per scheme) under FP32
+    transport, against the FP64 oracle."""
+    wl32 = _crop9("fp32", scheme, n_sub)
+    wl64 = _crop9("fp64", scheme, n_sub)
+    say(f"nine-species crop fp32 scheme {scheme} n_sub {n_sub}, 1000 steps")
     ctx, orc = _run(wl32, 1000), _oracle(wl64, 1000)
     errs = _errs(ctx, orc)
     say(errs)
@@ -137,6 +140,8 @@ def test_nine_species_crop_fp32_linearly_implicit_1000_steps():
             assert e <= 1e-5, (k, e)
         if k == "T" or k.startswith("Y"):
             assert e <= 1e-4, (k, e)
+    d = ctx.diagnostics()
+    assert d["n_flagged_fp64"] >= 1000 * wl32.cells  # every cell, every step
 
 
 def test_scheme_arguments_and_stability_rule():
