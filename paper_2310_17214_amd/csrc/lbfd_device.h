@@ -641,21 +641,32 @@ __device__ __forceinline__ void chem_step(const Par<double>& P, double& T, doubl
         constexpr int N1 = NSM + 1;
         const int cs = CS >= 0 ? CS : P.chem_scheme;
         if (cs == 1) {
+            // The temperature rows of J and f are -sum_k dh_k (species row
+            // k) / c_p, so the system's temperature equation reduces exactly
+            // to dT = sum_k c_k dY_k with c_k = -dh_k / c_p; substituted, it
+            // leaves the species system (I - h (J_YY + J_YT c^T)) dY = h f_Y,
+            // solved here in place of the full one (equal up to rounding).
             const double h = P.h_sub;
             for (int it = 0; it < P.n_sub; ++it) {
                 double J[N1][N1], b[N1];
                 rates_jacobian<NSM>(P, T, Y, eos<double, NSM>(P, T, Y), b, J);
+                double A[NSM][NSM], r[NSM];
 #pragma unroll
-                for (int i = 0; i < N1; ++i) {
+                for (int k = 0; k < NSM; ++k) {
 #pragma unroll
-                    for (int q = 0; q < N1; ++q) J[i][q] = -h * J[i][q];
-                    J[i][i] += 1.0;
-                    b[i] *= h;
+                    for (int m = 0; m < NSM; ++m)
+                        A[k][m] = -h * (J[k][m] - J[k][NSM] * (P.dhf[m] * P.inv_cp));
+                    A[k][k] += 1.0;
+                    r[k] = h * b[k];
                 }
-                solve_pivoted<N1>(J, b);
+                solve_pivoted<NSM>(A, r);
+                double dT = 0.0;
 #pragma unroll
-                for (int k = 0; k < NSM; ++k) Y[k] += b[k];
-                T += b[NSM];
+                for (int k = 0; k < NSM; ++k) {
+                    Y[k] += r[k];
+                    dT -= P.dhf[k] * P.inv_cp * r[k];
+                }
+                T += dT;
             }
             return;
         }
