@@ -415,15 +415,72 @@ __device__ __forceinline__ void chem_increments(const Par<C>& P, C T0, const C* 
 // (beta + theta/T)/T and d ln k_r / dT = d ln k_f / dT + b/T^2; then
 // d f_k/d Y_m = (M_k/M_m) sum_j s_kj d Q_j/d[X_m], d f_k/dT = (M_k/rho)
 // sum_j s_kj d Q_j/dT and row T = -sum_k dh_f,k (row k) / cp.
+// One reaction's terms for the Jacobian: the net rate Q_j, its temperature
+// derivative dQ_j/dT, and d Q_j / d[X_m] as the sum over the side factors q
+// with species index fi[q] (forward) and ri[q] (reverse): each factor of a
+// side contributes the product of the others (df[q], dr[q]); padding
+// factors carry the index NSM (concentration 1).
+template <int NSM>
+struct RxnTerms {
+    double Qj, dQT, df[4], dr[4];
+    int fi[4], ri[4];
+    // d Q_j / d[X_m]
+    __device__ __forceinline__ double dQ(int m) const {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v += fi[q] == m ? df[q] : 0.0;
+            v -= ri[q] == m ? dr[q] : 0.0;
+        }
+        return v;
+    }
+};
+template <int NSM>
+__device__ __forceinline__ RxnTerms<NSM> rxn_terms(const Par<double>& P, int j, const double* X,
+                                                   double lgT, double invT) {
+    const Rxn<double>& r = P.rx;
+    RxnTerms<NSM> t;
+    const int nf = j < P.n_lo ? 2 : 4;
+    const double kf = r.A[j] * fexp(r.beta[j] * lgT - r.theta[j] * invT);
+    const double dlf = (r.beta[j] + r.theta[j] * invT) * invT;
+    const bool rv = r.rev[j] != 0;
+    const double kr = rv ? kf * fexp(-(r.lnKc_a[j] + r.lnKc_b[j] * invT)) : 0.0;
+    const double dlr = dlf + r.lnKc_b[j] * invT * invT;
+    double xf[4], xr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        t.fi[q] = q < nf ? (int)((r.fidx[j] >> (8 * q)) & 255u) : NSM;
+        t.ri[q] = q < nf ? (int)((r.ridx[j] >> (8 * q)) & 255u) : NSM;
+        xf[q] = X[t.fi[q]];
+        xr[q] = X[t.ri[q]];
+    }
+    const double qf = kf * xf[0] * xf[1] * xf[2] * xf[3];
+    const double qr = kr * xr[0] * xr[1] * xr[2] * xr[3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double a = kf, b = kr;
+#pragma unroll
+        for (int o = 0; o < 4; ++o)
+            if (o != q) {
+                a *= xf[o];
+                b *= xr[o];
+            }
+        t.df[q] = a;
+        t.dr[q] = b;
+    }
+    t.Qj = qf - qr;
+    t.dQT = qf * dlf - qr * dlr;
+    return t;
+}
+
 template <int NSM>
 __device__ __forceinline__ void rates_jacobian(const Par<double>& P, double T, const double* Y,
                                                double rho, double* f,
                                                double (&J)[NSM + 1][NSM + 1]) {
     constexpr int N1 = NSM + 1;
-    // The sums over the reactions accumulate in the output arrays: f[k]
-    // takes sum_j s_kj Q_j, J[k][m] sum_j s_kj dQ_j/d[X_m] and J[k][NSM]
-    // sum_j s_kj dQ_j/dT, each scaled in place afterwards (one matrix in
-    // registers instead of two).
+    // the sums over the reactions accumulate in the outputs and are scaled
+    // in place afterwards: f[k] takes sum_j s_kj Q_j, J[k][m] sum_j s_kj
+    // dQ_j/d[X_m] and J[k][NSM] sum_j s_kj dQ_j/dT
     double X[NSM + 1];
 #pragma unroll
     for (int k = 0; k < NSM; ++k) {
@@ -435,56 +492,16 @@ __device__ __forceinline__ void rates_jacobian(const Par<double>& P, double T, c
     X[NSM] = 1.0;
     const double invT = 1.0 / T;
     const double lgT = P.any_beta ? flog(T) : 0.0;
-    const Rxn<double>& r = P.rx;
     for (int j = 0; j < P.n_tab; ++j) {
-        const int nf = j < P.n_lo ? 2 : 4;
-        const double kf = r.A[j] * fexp(r.beta[j] * lgT - r.theta[j] * invT);
-        const double dlf = (r.beta[j] + r.theta[j] * invT) * invT;
-        const bool rv = r.rev[j] != 0;
-        const double kr = rv ? kf * fexp(-(r.lnKc_a[j] + r.lnKc_b[j] * invT)) : 0.0;
-        const double dlr = dlf + r.lnKc_b[j] * invT * invT;
-        int fi[4], ri[4];
-        double xf[4], xr[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            fi[q] = q < nf ? (int)((r.fidx[j] >> (8 * q)) & 255u) : NSM;
-            ri[q] = q < nf ? (int)((r.ridx[j] >> (8 * q)) & 255u) : NSM;
-            xf[q] = X[fi[q]];
-            xr[q] = X[ri[q]];
-        }
-        const double qf = kf * xf[0] * xf[1] * xf[2] * xf[3];
-        const double qr = kr * xr[0] * xr[1] * xr[2] * xr[3];
-        // d Q / d[X_m]: each factor q of a side contributes the product of the others
-        double df[4], dr[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            double a = kf, b = kr;
-#pragma unroll
-            for (int o = 0; o < 4; ++o)
-                if (o != q) {
-                    a *= xf[o];
-                    b *= xr[o];
-                }
-            df[q] = a;
-            dr[q] = b;
-        }
+        const RxnTerms<NSM> t = rxn_terms<NSM>(P, j, X, lgT, invT);
         double dQ[NSM];
 #pragma unroll
-        for (int m = 0; m < NSM; ++m) {
-            double v = 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                v += fi[q] == m ? df[q] : 0.0;
-                v -= ri[q] == m ? dr[q] : 0.0;
-            }
-            dQ[m] = v;
-        }
-        const double Qj = qf - qr, dQT = qf * dlf - qr * dlr;
+        for (int m = 0; m < NSM; ++m) dQ[m] = t.dQ(m);
 #pragma unroll
         for (int k = 0; k < NSM; ++k) {
-            const double s = r.nud[j][k];
-            f[k] += s * Qj;
-            J[k][NSM] += s * dQT;
+            const double s = P.rx.nud[j][k];
+            f[k] += s * t.Qj;
+            J[k][NSM] += s * t.dQT;
 #pragma unroll
             for (int m = 0; m < NSM; ++m) J[k][m] += s * dQ[m];
         }
@@ -524,50 +541,13 @@ __device__ __forceinline__ void rates_jacobian_diag(const Par<double>& P, double
     X[NSM] = 1.0;
     const double invT = 1.0 / T;
     const double lgT = P.any_beta ? flog(T) : 0.0;
-    const Rxn<double>& r = P.rx;
     for (int j = 0; j < P.n_tab; ++j) {
-        const int nf = j < P.n_lo ? 2 : 4;
-        const double kf = r.A[j] * fexp(r.beta[j] * lgT - r.theta[j] * invT);
-        const double dlf = (r.beta[j] + r.theta[j] * invT) * invT;
-        const bool rv = r.rev[j] != 0;
-        const double kr = rv ? kf * fexp(-(r.lnKc_a[j] + r.lnKc_b[j] * invT)) : 0.0;
-        const double dlr = dlf + r.lnKc_b[j] * invT * invT;
-        int fi[4], ri[4];
-        double xf[4], xr[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            fi[q] = q < nf ? (int)((r.fidx[j] >> (8 * q)) & 255u) : NSM;
-            ri[q] = q < nf ? (int)((r.ridx[j] >> (8 * q)) & 255u) : NSM;
-            xf[q] = X[fi[q]];
-            xr[q] = X[ri[q]];
-        }
-        const double qf = kf * xf[0] * xf[1] * xf[2] * xf[3];
-        const double qr = kr * xr[0] * xr[1] * xr[2] * xr[3];
-        double df[4], dr[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            double a = kf, b = kr;
-#pragma unroll
-            for (int o = 0; o < 4; ++o)
-                if (o != q) {
-                    a *= xf[o];
-                    b *= xr[o];
-                }
-            df[q] = a;
-            dr[q] = b;
-        }
-        const double dQT = qf * dlf - qr * dlr;
+        const RxnTerms<NSM> t = rxn_terms<NSM>(P, j, X, lgT, invT);
 #pragma unroll
         for (int k = 0; k < NSM; ++k) {
-            double v = 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                v += fi[q] == k ? df[q] : 0.0;
-                v -= ri[q] == k ? dr[q] : 0.0;
-            }
-            const double s = r.nud[j][k];
-            GT[k] += s * dQT;
-            G[k] += s * v;
+            const double s = P.rx.nud[j][k];
+            GT[k] += s * t.dQT;
+            G[k] += s * t.dQ(k);
         }
     }
     const double irho = 1.0 / rho;
